@@ -1,0 +1,326 @@
+"""FP64 CPU oracle for multi-wavelength diffractive propagation and its gradient.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import or run this module.  The product path
+(the HIP library and its Python binding) never calls it, and this module
+imports nothing from the product package.
+
+What it computes (paper, Section 4 "Optical forward model of
+wavelength-multiplexed diffractive systems", Eq. 1, 2, 4, 5; problem
+statement in Section 2 and the Fig. 1 caption):
+
+* every wavelength lambda_w starts from the input field u_in (unit plane wave
+  by default: the paper's "uniform input fields"),
+* each of the K layers multiplies the field by the transmission of Eq. 1,
+  t = exp(-2 pi kappa h / lambda) * exp(+j 2 pi (n - n_m) h / lambda),
+  h being the total thickness of Eq. 2 (the sign reading is explained below),
+* the field then travels the gap z_l by the Rayleigh-Sommerfeld convolution of
+  Eq. 4/5, evaluated here by the angular spectrum: zero-pad N -> M = pad*N
+  (centred), 2-D DFT, multiply by H = exp(+j 2 pi z sqrt(q)) with
+  q = (n_m/lambda)^2 - fx^2 - fy^2 where q > 0 and H = 0 elsewhere (the
+  evanescent part is cut), inverse DFT (1/M^2), crop back to N x N,
+* the output intensity O_w = |o_w|^2 is cropped to the central F x F
+  field of view and summed over bin x bin blocks into a T x T image,
+* loss: per wavelength the intensity and the target are each normalised to
+  unit sum, the mean squared difference over the T^2 pixels is taken, and the
+  mean over wavelengths is the loss (the paper's MSE-based loss; its exact
+  form lives in a supplement that is not available),
+* gradient: reverse-mode (adjoint) pass written by hand in FP64.
+
+Readings of the paper used here (each also listed with the design notes):
+
+* Eq. 1 prints exp(-j 2 pi (n - n_air) h / lambda) next to the absorption
+  factor exp(-2 pi kappa h / lambda); that absorption sign is only consistent
+  with the exp(+j k r) outgoing-wave convention of Eq. 4, under which optical
+  path adds phase exp(+j 2 pi (n - n_air) h / lambda).  We use +j.  The
+  printed sign equals ours with h -> -h (kappa = 0).
+* "n" in Eq. 4 is the index of the gap medium n_m (air, n_m = 1); n_air in
+  Eq. 1 is the same n_m.
+* Eq. 5 has no area element; the direct Rayleigh-Sommerfeld sum below
+  multiplies by dx^2 so that it approximates the continuous integral.  The
+  angular spectrum needs none (unitary DFT pair).
+* The field outside the N x N layer aperture is dropped after every gap.
+
+DFT conventions: forward kernel exp(-2 pi j k n / M) with exact integer
+reduction (k n mod M) before the angle is formed, unnormalised; the inverse
+carries 1/M^2.  Frequencies are fx = k'/(M dx) with k' the signed index in
+[-M/2, M/2).
+
+Two evaluation modes for the 2-D DFT: ``"naive"`` forms the DFT matrix from
+its definition and applies it with matrix products; ``"fft"`` calls
+``numpy.fft`` (pocketfft, FP64).  Both are pinned against each other and
+against closed forms by the oracle tests.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+# ------------------------------------------------------------------------------------------
+# Discrete Fourier transform (Section 4: the gap propagation is a linear shift-invariant
+# convolution, Eq. 5; here evaluated through the DFT).
+# ------------------------------------------------------------------------------------------
+
+def signed_index(M: int) -> np.ndarray:
+    """k' = k for k < M/2, k - M otherwise (the order numpy.fft.fftfreq uses)."""
+    k = np.arange(M, dtype=np.int64)
+    return np.where(k < (M + 1) // 2, k, k - M)
+
+
+def dft_matrix(M: int) -> np.ndarray:
+    """F[k, n] = exp(-2 pi j ((k n) mod M) / M)."""
+    n = np.arange(M, dtype=np.int64)
+    idx = np.outer(n, n) % M
+    return np.exp(-1j * TWO_PI * idx.astype(np.float64) / M)
+
+
+_DFT_CACHE: dict[int, np.ndarray] = {}
+
+
+def _dft(M):
+    F = _DFT_CACHE.get(M)
+    if F is None:
+        F = dft_matrix(M)
+        _DFT_CACHE[M] = F
+    return F
+
+
+def dft2(U: np.ndarray, mode: str = "naive") -> np.ndarray:
+    """Unnormalised 2-D DFT over the last two axes (square)."""
+    if mode == "fft":
+        return np.fft.fft2(U, axes=(-2, -1))
+    F = _dft(U.shape[-1])
+    return F @ U @ F.T
+
+
+def idft2(V: np.ndarray, mode: str = "naive") -> np.ndarray:
+    """Inverse 2-D DFT with the 1/M^2 factor."""
+    if mode == "fft":
+        return np.fft.ifft2(V, axes=(-2, -1))
+    M = V.shape[-1]
+    G = np.conj(_dft(M))
+    return (G @ V @ G.T) / float(M * M)
+
+
+# ------------------------------------------------------------------------------------------
+# Transfer function of the gap (Eq. 4 in the spectral domain).
+# ------------------------------------------------------------------------------------------
+
+def spatial_frequencies(M: int, dx: float) -> np.ndarray:
+    return signed_index(M).astype(np.float64) / (M * dx)
+
+
+def transfer_function(M: int, dx: float, wl: float, n_medium: float, z: float) -> np.ndarray:
+    """H[ky, kx] = exp(+j 2 pi z sqrt(q)) for q = (n_m/lambda)^2 - fx^2 - fy^2 > 0, else 0."""
+    f = spatial_frequencies(M, dx)
+    q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
+    prop = q > 0.0
+    root = np.sqrt(np.where(prop, q, 0.0))
+    return np.where(prop, np.exp(1j * TWO_PI * z * root), 0.0)
+
+
+def pad_centered(u: np.ndarray, M: int) -> np.ndarray:
+    N = u.shape[-1]
+    o = (M - N) // 2
+    U = np.zeros(u.shape[:-2] + (M, M), dtype=np.complex128)
+    U[..., o:o + N, o:o + N] = u
+    return U
+
+
+def crop_centered(U: np.ndarray, N: int) -> np.ndarray:
+    M = U.shape[-1]
+    o = (M - N) // 2
+    return U[..., o:o + N, o:o + N]
+
+
+def propagate(u: np.ndarray, pad: int, dx: float, wl: float, n_medium: float, z: float,
+              mode: str = "naive", adjoint: bool = False) -> np.ndarray:
+    """One gap: pad -> DFT2 -> x H -> IDFT2 -> crop.  ``adjoint`` applies the Hermitian
+    adjoint of that linear map, which is the same chain with conj(H)."""
+    N = u.shape[-1]
+    M = pad * N
+    H = transfer_function(M, dx, wl, n_medium, z)
+    if adjoint:
+        H = np.conj(H)
+    V = idft2(H * dft2(pad_centered(u, M), mode), mode)
+    return crop_centered(V, N)
+
+
+# ------------------------------------------------------------------------------------------
+# Layer transmission (Eq. 1, 2).
+# ------------------------------------------------------------------------------------------
+
+def layer_constants(wl: float, n_mat: float, kappa: float, n_medium: float):
+    """(c_t, c_a): phase and absorption per metre of thickness, Eq. 1."""
+    c_t = TWO_PI * (n_mat - n_medium) / wl
+    c_a = TWO_PI * kappa / wl
+    return c_t, c_a
+
+
+def transmission(h: np.ndarray, wl: float, n_mat: float, kappa: float, n_medium: float):
+    c_t, c_a = layer_constants(wl, n_mat, kappa, n_medium)
+    h = np.asarray(h, dtype=np.float64)
+    return np.exp(-c_a * h) * np.exp(1j * c_t * h)
+
+
+# ------------------------------------------------------------------------------------------
+# Cascade, intensity, loss, gradient.
+# ------------------------------------------------------------------------------------------
+
+def _kappa(design, w):
+    k = design.get("kappa")
+    return 0.0 if k is None else float(k[w])
+
+
+def fov_slice(design):
+    N, F = design["n"], design["fov"]
+    a = (N - F) // 2
+    return slice(a, a + F)
+
+
+def bin_sum(x: np.ndarray, b: int) -> np.ndarray:
+    F = x.shape[-1]
+    T = F // b
+    return x.reshape(x.shape[:-2] + (T, b, T, b)).sum(axis=(-3, -1))
+
+
+def forward(design: dict, h: np.ndarray, u_in=None, mode: str = "naive", keep: bool = False,
+            wavelengths=None):
+    """Intensity images I[w, T, T] for every wavelength (Eq. 5 recursion, then |o|^2 on the
+    field of view).  With ``keep`` also return the per-layer fields after the transmission
+    multiply (v[w, l]) and the output field on the field of view (o[w])."""
+    N, K = design["n"], design["layers"]
+    ws = range(design["n_wl"]) if wavelengths is None else list(wavelengths)
+    fs = fov_slice(design)
+    b = design["bin"]
+    T = design["fov"] // b
+    h64 = np.asarray(h, dtype=np.float64)
+    u0 = np.ones((N, N), np.complex128) if u_in is None else np.asarray(u_in, np.complex128)
+    out = np.zeros((len(ws), T, T), dtype=np.float64)
+    vs = np.zeros((len(ws), K, N, N), np.complex128) if keep else None
+    os_ = np.zeros((len(ws), design["fov"], design["fov"]), np.complex128) if keep else None
+    for i, w in enumerate(ws):
+        wl, nm = float(design["wl"][w]), float(design["n_mat"][w])
+        u = u0
+        for l in range(K):
+            v = transmission(h64[l], wl, nm, _kappa(design, w), design["n_medium"]) * u
+            if keep:
+                vs[i, l] = v
+            u = propagate(v, design["pad"], design["dx"], wl, design["n_medium"],
+                          float(design["z"][l]), mode)
+        o = u[fs, fs]
+        if keep:
+            os_[i] = o
+        out[i] = bin_sum(np.abs(o) ** 2, b)
+    if keep:
+        return out, vs, os_
+    return out
+
+
+def loss(I: np.ndarray, tau: np.ndarray):
+    """L = (1/W) sum_w mean_p (I_w,p / S_w - tau_w,p / sum tau_w)^2 and dL/dI.
+
+    A wavelength whose intensity (or target) sums to zero contributes a zero ratio and a
+    zero gradient."""
+    I = np.asarray(I, np.float64)
+    tau = np.asarray(tau, np.float64)
+    W = I.shape[0]
+    P = I.shape[-1] * I.shape[-2]
+    S = I.sum(axis=(1, 2))
+    St = tau.sum(axis=(1, 2))
+    Ih = np.where(S[:, None, None] > 0, I / np.where(S > 0, S, 1.0)[:, None, None], 0.0)
+    th = np.where(St[:, None, None] > 0, tau / np.where(St > 0, St, 1.0)[:, None, None], 0.0)
+    d = Ih - th
+    per_wl = (d * d).sum(axis=(1, 2)) / P
+    L = per_wl.sum() / W
+    inner = (d * Ih).sum(axis=(1, 2))
+    g = 2.0 / (W * P) * (d - inner[:, None, None])
+    g = np.where(S[:, None, None] > 0, g / np.where(S > 0, S, 1.0)[:, None, None], 0.0)
+    return float(L), g, per_wl
+
+
+def grad(design: dict, h: np.ndarray, u_in, dl_di: np.ndarray, mode: str = "naive",
+         wavelengths=None):
+    """dL/dh[l, y, x] for the given dL/dI[w, T, T] (summed over wavelengths in index order).
+
+    Wirtinger convention: g = dL/dRe(u) + j dL/dIm(u).  Output seed g = 2 (dL/dI) o on the
+    field of view.  Back through a gap: g <- P^H g.  At layer l with v = t u:
+    dL/dh += -c_t Im(conj(g) v) - c_a Re(conj(g) v), then g <- conj(t) g."""
+    N, K = design["n"], design["layers"]
+    ws = list(range(design["n_wl"])) if wavelengths is None else list(wavelengths)
+    fs = fov_slice(design)
+    b = design["bin"]
+    _, vs, os_ = forward(design, h, u_in, mode, keep=True, wavelengths=ws)
+    h64 = np.asarray(h, dtype=np.float64)
+    dh = np.zeros((K, N, N), np.float64)
+    for i, w in enumerate(ws):
+        wl, nm = float(design["wl"][w]), float(design["n_mat"][w])
+        c_t, c_a = layer_constants(wl, nm, _kappa(design, w), design["n_medium"])
+        dI = np.repeat(np.repeat(np.asarray(dl_di[i], np.float64), b, axis=0), b, axis=1)
+        g = np.zeros((N, N), np.complex128)
+        g[fs, fs] = 2.0 * dI * os_[i]
+        for l in range(K - 1, -1, -1):
+            g = propagate(g, design["pad"], design["dx"], wl, design["n_medium"],
+                          float(design["z"][l]), mode, adjoint=True)
+            p = np.conj(g) * vs[i, l]
+            dh[l] += -c_t * p.imag - c_a * p.real
+            g = np.conj(transmission(h64[l], wl, nm, _kappa(design, w), design["n_medium"])) * g
+    return dh
+
+
+def loss_of_heights(design, h, u_in, tau, mode="naive", wavelengths=None):
+    I = forward(design, h, u_in, mode, wavelengths=wavelengths)
+    t = tau if wavelengths is None else np.asarray(tau)[list(wavelengths)]
+    return loss(I, t)[0]
+
+
+def fd_pixels(design, h, u_in, tau, pixels, delta, mode="naive"):
+    """Central differences of the loss w.r.t. single heights h[l, y, x] (FP64)."""
+    h64 = np.asarray(h, dtype=np.float64)
+    out = np.zeros(len(pixels))
+    for i, (l, y, x) in enumerate(pixels):
+        hp = h64.copy()
+        hm = h64.copy()
+        hp[l, y, x] += delta
+        hm[l, y, x] -= delta
+        out[i] = (loss_of_heights(design, hp, u_in, tau, mode)
+                  - loss_of_heights(design, hm, u_in, tau, mode)) / (2 * delta)
+    return out
+
+
+def fd_direction(design, h, u_in, tau, v, delta, mode="naive"):
+    """Central difference of the loss along the direction v (same shape as h)."""
+    h64 = np.asarray(h, dtype=np.float64)
+    lp = loss_of_heights(design, h64 + delta * v, u_in, tau, mode)
+    lm = loss_of_heights(design, h64 - delta * v, u_in, tau, mode)
+    return (lp - lm) / (2 * delta)
+
+
+# ------------------------------------------------------------------------------------------
+# Direct Rayleigh-Sommerfeld sum (Eq. 4, 5) for tiny grids.
+# ------------------------------------------------------------------------------------------
+
+def rs_kernel(dxs: np.ndarray, dys: np.ndarray, z: float, wl: float, n_medium: float):
+    """w = z / r^2 (1/(2 pi r) + n / (j lambda)) exp(j 2 pi n r / lambda), Eq. 4."""
+    r = np.sqrt(dxs * dxs + dys * dys + z * z)
+    return z / (r * r) * (1.0 / (TWO_PI * r) + n_medium / (1j * wl)) * np.exp(
+        1j * TWO_PI * n_medium * r / wl)
+
+
+def rs_direct(u: np.ndarray, dx: float, wl: float, n_medium: float, z: float) -> np.ndarray:
+    """u_out(p) = sum_s u(s) w(p - s) dx^2 on the same N x N lateral grid, O(N^4)."""
+    N = u.shape[-1]
+    d = (np.arange(2 * N - 1) - (N - 1)).astype(np.float64) * dx
+    Kd = rs_kernel(d[None, :], d[:, None], z, wl, n_medium) * dx * dx   # [dy, dx]
+    # Toeplitz blocks T[dy][px, sx] = Kd[dy, px - sx + N - 1]
+    px = np.arange(N)
+    cols = px[:, None] - px[None, :] + N - 1
+    T = Kd[:, cols]                                                      # [2N-1, N, N]
+    out = np.zeros((N, N), np.complex128)
+    sy = np.arange(N)
+    for py in range(N):
+        blocks = T[py - sy + N - 1]                                      # [N(sy), N(px), N(sx)]
+        out[py] = np.einsum("spk,sk->p", blocks, u)
+    return out

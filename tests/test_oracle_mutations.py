@@ -1,0 +1,103 @@
+"""The oracle pins must fail on plausible mistakes.  Each case plants one slip in the oracle
+(monkeypatched, CPU only, undone after the test) and checks that at least one pin rejects it."""
+import numpy as np
+import pytest
+
+import tests.test_oracle_pins as pins
+from oracle import dpx_oracle as o
+
+TWO_PI = 2 * np.pi
+
+
+def _h_sign_flipped(M, dx, wl, n_medium, z):
+    f = o.spatial_frequencies(M, dx)
+    q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
+    return np.where(q > 0, np.exp(-1j * TWO_PI * z * np.sqrt(np.maximum(q, 0))), 0)
+
+
+def _h_no_cut(M, dx, wl, n_medium, z):
+    f = o.spatial_frequencies(M, dx)
+    q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
+    return np.exp(1j * TWO_PI * z * np.sqrt(q.astype(complex)))
+
+
+def _h_axes_scaled(M, dx, wl, n_medium, z):
+    f = o.spatial_frequencies(M, dx)
+    q = (n_medium / wl) ** 2 - f[None, :] ** 2 - 0.5 * f[:, None] ** 2
+    return np.where(q > 0, np.exp(1j * TWO_PI * z * np.sqrt(np.maximum(q, 0))), 0)
+
+
+def _idft_no_norm(V, mode="naive"):
+    return np.fft.ifft2(V, axes=(-2, -1)) * V.shape[-1]
+
+
+def _crop_shifted(U, N):
+    return U[..., 1:1 + N, 1:1 + N]
+
+
+def _t_sign_flipped(h, wl, n_mat, kappa, n_medium):
+    c_t, c_a = o.layer_constants(wl, n_mat, kappa, n_medium)
+    return np.exp(-c_a * np.asarray(h, float)) * np.exp(-1j * c_t * np.asarray(h, float))
+
+
+def _t_index_not_relative(h, wl, n_mat, kappa, n_medium):
+    h = np.asarray(h, float)
+    return np.exp(1j * TWO_PI * n_mat * h / wl)
+
+
+def _loss_missing_inner(I, tau):
+    L, g, per = _orig_loss(I, tau)
+    I = np.asarray(I, float)
+    S = I.sum(axis=(1, 2))
+    W, P = I.shape[0], I.shape[1] * I.shape[2]
+    d = I / S[:, None, None] - tau / tau.sum(axis=(1, 2))[:, None, None]
+    return L, 2.0 / (W * P) * d / S[:, None, None], per
+
+
+_orig_loss = o.loss
+
+CASES = [
+    ("transfer_function", _h_sign_flipped, [pins.test_tilted_plane_wave, (3, 0)]),
+    ("transfer_function", _h_no_cut, [pins.test_evanescent_wave_is_cut_even_at_short_range]),
+    ("transfer_function", _h_axes_scaled, [pins.test_tilted_plane_wave, (0, 5)]),
+    ("idft2", _idft_no_norm, [pins.test_normal_plane_wave_picks_up_exp_jkz]),
+    ("crop_centered", _crop_shifted, [pins.test_mirror_symmetry_and_linearity]),
+    ("transmission", _t_sign_flipped, [pins.test_prism_deflects_toward_thicker_side]),
+    ("transmission", _t_index_not_relative, [pins.test_prism_deflects_toward_thicker_side]),
+    ("loss", _loss_missing_inner, [pins.test_loss_gradient_finite_difference_and_euler]),
+]
+
+
+@pytest.mark.parametrize("name,mutant,check", CASES,
+                         ids=[f"{c[0]}:{c[1].__name__}" for c in CASES])
+def test_pin_rejects_mutant(monkeypatch, name, mutant, check):
+    monkeypatch.setattr(o, name, mutant)
+    fn, *args = check
+    with pytest.raises(AssertionError):
+        fn(*(args[0] if args else ()))
+
+
+def test_gradient_pin_rejects_dropped_absorption_term(monkeypatch):
+    """Adjoint that forgets the -c_a Re(conj(g) v) term of dL/dh (only matters with kappa > 0)."""
+    orig = o.layer_constants
+
+    def grad_without_ca(design, h, u_in, dl_di, mode="naive", wavelengths=None):
+        N, K = design["n"], design["layers"]
+        _, vs, os_ = o.forward(design, h, u_in, mode, keep=True)
+        out = np.zeros((K, N, N))
+        fs = o.fov_slice(design)
+        for w in range(design["n_wl"]):
+            wl, nm, ka = float(design["wl"][w]), float(design["n_mat"][w]), float(design["kappa"][w])
+            c_t, _ = orig(wl, nm, ka, design["n_medium"])
+            g = np.zeros((N, N), complex)
+            g[fs, fs] = 2.0 * dl_di[w] * os_[w]
+            for l in range(K - 1, -1, -1):
+                g = o.propagate(g, design["pad"], design["dx"], wl, design["n_medium"],
+                                float(design["z"][l]), mode, adjoint=True)
+                out[l] += -c_t * (np.conj(g) * vs[w, l]).imag
+                g = np.conj(o.transmission(h[l], wl, nm, ka, design["n_medium"])) * g
+        return out
+
+    monkeypatch.setattr(o, "grad", grad_without_ca)
+    with pytest.raises(AssertionError):
+        pins.test_gradient_matches_central_differences(True, 1)
