@@ -1,0 +1,267 @@
+#!/usr/bin/env python
+"""Throughput of the fused multi-wavelength forward + loss + adjoint on one MI355X.
+
+One step = dpx_forward + dpx_loss + dpx_backward over the whole workload (every wavelength,
+every layer), inputs resident in device memory.  The metric is wavelength-layer propagations
+per second counted forward + adjoint: W * K / step time.
+
+Default workload: 4 layers of 512 x 512 features zero-padded to 1024 x 1024, 4096 wavelengths
+uniform in 450-750 nm, Cauchy n(lambda), 30 um gaps, 64 x 64 grayscale targets, store-mode
+checkpoints.  Inputs are seeded synthetic arrays (paper_2604_02624_amd.workloads).
+
+Printed: one JSON line with the throughput, the live roofline of the dominant kernel (HIP
+events around each of its launches inside the timed region, algorithmic bytes per launch),
+the FP64 CPU oracle timed on a bounded sample of the same workload, and a plain per-wavelength
+torch FFT loop (rocFFT + autograd) timed on a sample of wavelengths on the same GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "wavelength·layer propagations/s (fwd+adjoint) + % HBM roofline vs plain loop"
+UNIT = "propagations/s"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2604_02624_amd/csrc/dpx_kernels.hip", "paper_2604_02624_amd/csrc/fft.hpp"]
+WORKLOAD_NAMES = {
+    1: "small forward: 2 layers 64x64 (pad 128), 6 wavelengths 500-740 nm",
+    2: "small fwd+adjoint: 2 layers 64x64 (pad 128), 6 wavelengths 500-740 nm, binary targets",
+    3: "batched fwd+adjoint: 5 layers 256x256 (pad 512), 256 wavelengths 450-750 nm",
+    4: "large fwd+adjoint: 4 layers 512x512 (pad 1024), 4096 wavelengths 450-750 nm, 64x64 targets",
+    5: "uneven fwd+adjoint: 64 designs, N in {96,128,192,256} (pad 2N), 2-5 layers, 6-512 wavelengths",
+}
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------------------------------
+# plain per-wavelength loop on the same GPU: pad -> fft2 -> x H -> ifft2 -> crop, torch
+# autograd for the gradient.  H is precomputed per wavelength and layer outside the timing.
+# ------------------------------------------------------------------------------------------
+def plain_loop_rate(torch, d, h, tau, n_sample, device):
+    import numpy as np
+    N, M, K, F = d["n"], d["pad"] * d["n"], d["layers"], d["fov"]
+    W = d["n_wl"]
+    idx = np.linspace(0, W - 1, n_sample).round().astype(int)
+    f = torch.fft.fftfreq(M, d=d["dx"], dtype=torch.float64, device=device)
+    f2 = f[None, :] ** 2 + f[:, None] ** 2
+    Hs = {}
+    for w in idx:
+        for l in range(K):
+            q = (d["n_medium"] / d["wl"][w]) ** 2 - f2
+            ph = 2 * np.pi * d["z"][l] * torch.sqrt(torch.clamp(q, min=0))
+            Hs[(w, l)] = torch.where(q > 0, torch.polar(torch.ones_like(ph), ph),
+                                     torch.zeros((), dtype=torch.complex128, device=device)
+                                     ).to(torch.complex64)
+    ht = torch.as_tensor(h, device=device).requires_grad_(True)
+    taut = torch.as_tensor(tau, device=device)
+    a = (N - F) // 2
+
+    def one_pass():
+        ht.grad = None
+        total = 0.0
+        for w in idx:
+            kt = float(2 * np.pi * (d["n_mat"][w] - d["n_medium"]) / d["wl"][w])
+            u = torch.ones((N, N), dtype=torch.complex64, device=device)
+            for l in range(K):
+                u = u * torch.polar(torch.ones_like(ht[l]), kt * ht[l])
+                U = torch.zeros((M, M), dtype=torch.complex64, device=device)
+                U[:N, :N] = u
+                u = torch.fft.ifft2(torch.fft.fft2(U) * Hs[(w, l)])[:N, :N]
+            I = u[a:a + F, a:a + F].abs() ** 2
+            t = taut[w]
+            Lw = ((I / I.sum() - t / t.sum()) ** 2).mean() / W
+            Lw.backward()
+            total += float(0)
+        return total
+
+    one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one_pass()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return n_sample * K / dt, dt
+
+
+# ------------------------------------------------------------------------------------------
+# FP64 CPU oracle on a bounded sample of the workload
+# ------------------------------------------------------------------------------------------
+def cpu_baseline(d, h, tau, budget_s):
+    import numpy as np
+    from oracle import dpx_oracle as o
+    W, K = d["n_wl"], d["layers"]
+    order = np.random.default_rng(7).permutation(W)
+    done, t0 = 0, time.perf_counter()
+    while done < 2 or (time.perf_counter() - t0 < budget_s and done < W):
+        w = int(order[done])
+        I = o.forward(d, h, None, "fft", wavelengths=[w])
+        _, g, _ = o.loss(I, tau[[w]])
+        o.grad(d, h, None, g, "fft", wavelengths=[w])
+        done += 1
+    dt = time.perf_counter() - t0
+    return dict(value=done * K / dt, unit=UNIT, cores=1, kind="oracle",
+                sample=f"{done} wavelengths x {K} layers of the same workload, forward + loss + "
+                       f"adjoint, numpy.fft (pocketfft, single thread) FP64, {dt:.1f} s")
+
+
+def traffic_from_profiles(pass_name, launches_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
+    current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{pass_name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--checkpoint-mode", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--wl-chunk", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--plain-sample", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain-loop", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "the path shards over wavelengths with one all-reduce of dL/dh, which this build does "
+              "not run across GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2604_02624_amd import dpx, workloads as wk
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"[bench] workload {args.workload}: {WORKLOAD_NAMES[args.workload]}")
+    w = wk.make_workload(args.workload)
+    designs = w["designs"]
+    plan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
+                    force_variant=args.variant)
+    h = plan.pack_heights(w["h"])
+    tau = plan.pack_images(w["targets"])
+    I = torch.empty(plan.img_count, dtype=torch.float32, device=dev)
+    g = torch.empty(plan.img_count, dtype=torch.float32, device=dev)
+    L = torch.empty(len(designs), dtype=torch.float64, device=dev)
+    dh = torch.empty(plan.h_count, dtype=torch.float32, device=dev)
+    props = sum(d["n_wl"] * d["layers"] for d in designs)
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
+
+    def step():
+        plan.forward(h, None, I)
+        plan.loss(I, tau, L, g)
+        plan.backward(h, None, g, dh)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+
+    plan.timing(True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"[bench] {args.steps} timed steps done in {wall:.3f} s")
+    passes = plan.timing_read()
+    plan.timing(False)
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = props / (ms_step / 1e3)
+
+    # dominant kernel: the pass with the largest summed time
+    dom = max(passes, key=lambda k: passes[k]["ms"])
+    pd = passes[dom]
+    per_launch_s = pd["ms"] / 1e3 / max(pd["launches"], 1)
+    bytes_per_launch = pd["bytes"] / max(pd["launches"], 1)
+    achieved = bytes_per_launch / per_launch_s / 1e9
+    traffic = traffic_from_profiles(dom, bytes_per_launch)
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    algorithmic_bytes_per_launch=int(bytes_per_launch),
+                    avg_launch_ms=round(per_launch_s * 1e3, 4), launches=pd["launches"])
+    pass_summary = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3),
+                            gbs=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None)
+                    for k, v in passes.items() if v["launches"]}
+    # sanity: the loss is finite
+    Lh = L.cpu().numpy()
+    if not np.isfinite(Lh).all():
+        raise RuntimeError(f"non-finite loss {Lh}")
+
+    plain = None
+    if not args.no_plain_loop and len(designs) == 1:
+        log(f"[bench] plain per-wavelength torch loop on {args.plain_sample} wavelengths")
+        rate, dt = plain_loop_rate(torch, designs[0], w["h"][0], w["targets"][0],
+                                   min(args.plain_sample, designs[0]["n_wl"]), dev)
+        plain = dict(value=round(rate, 1), unit=UNIT,
+                     sample=f"{min(args.plain_sample, designs[0]['n_wl'])} wavelengths, torch.fft "
+                            f"(rocFFT) + autograd, complex64, one wavelength at a time, {dt:.2f} s")
+
+    cpu = None
+    if not args.no_cpu_baseline and len(designs) == 1:
+        log(f"[bench] FP64 oracle on the host for about {args.cpu_seconds:.0f} s")
+        cpu = cpu_baseline(designs[0], w["h"][0], w["targets"][0], args.cpu_seconds)
+        cpu["value"] = round(cpu["value"], 3)
+
+    d0 = designs[0]
+    out = dict(
+        metric=METRIC, value=round(value, 1), unit=UNIT, n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload=WORKLOAD_NAMES[args.workload], designs=len(designs),
+                    wavelengths=sum(d["n_wl"] for d in designs), layers=d0["layers"], n=d0["n"],
+                    transform=d0["n"] * d0["pad"], checkpoint_mode=args.checkpoint_mode,
+                    wl_chunk=args.wl_chunk, phase_args="f64"),
+        roofline=roofline, cpu_baseline=cpu, plain_loop=plain,
+        vs_plain_loop=(round(value / plain["value"], 2) if plain else None),
+        passes=pass_summary, wall_s=round(wall, 3),
+    )
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * dpx — multi-wavelength diffractive propagation through cascaded dielectric phase layers
+ * and its gradient, on AMD Instinct MI355X (gfx950).
+ *
+ * What the calls compute (paper: "Wavelength-multiplexed massively parallel diffractive
+ * optical information storage and image projection", Section 4 "Optical forward model",
+ * Eq. 1, 2, 4, 5; problem statement in Section 2 and the Fig. 1 caption):
+ *
+ *   for every wavelength lambda_w of a design, starting from the input field u_in:
+ *     for layer l = 0 .. K-1:
+ *       u <- u * t_l,   t_l = exp(-2 pi kappa h_l / lambda) exp(+j 2 pi (n - n_m) h_l / lambda)
+ *       u <- P_l u      (Rayleigh-Sommerfeld propagation over the gap z[l], Eq. 4/5,
+ *                        evaluated by the angular spectrum: zero-pad N -> pad*N, 2-D FFT,
+ *                        multiply by H = exp(+j 2 pi z sqrt(q)) where
+ *                        q = (n_m/lambda)^2 - fx^2 - fy^2 > 0 and 0 elsewhere,
+ *                        inverse FFT, keep the N x N aperture)
+ *     intensity I_w = |u|^2 on the central fov x fov window, summed over bin x bin blocks.
+ *
+ *   loss (per design): L = (1/W) sum_w (1/T^2) sum_p (I_w,p / sum_p I_w,p
+ *                                                     - tau_w,p / sum_p tau_w,p)^2
+ *   (the paper's MSE-based loss between projected intensity images and their targets, with
+ *    both normalised to unit sum; a wavelength whose intensity or target sums to zero
+ *    contributes a zero ratio and a zero gradient.)
+ *
+ *   backward: dL/dh for every height of every layer given dL/dI (hand-written adjoint:
+ *   conjugate transfer function, reverse transforms, d t / d h).
+ *
+ * The +j sign of the transmission phase is the reading consistent with the exp(+j k r)
+ * outgoing wave of Eq. 4 (the printed Eq. 1 carries -j; with kappa = 0 that is the same model
+ * with h -> -h).  n_m is the index of the gap medium ("n" of Eq. 4 and n_air of Eq. 1).
+ *
+ * Conventions shared by every call:
+ *   - Lengths are in metres.  Heights h are float32, fields complex64 stored as interleaved
+ *     float pairs (re, im), images float32, all row-major with x fastest.
+ *   - Buffers are packed over the plan's designs in design order:
+ *        h, dl_dh        : sum_d K_d * N_d * N_d floats          ([K][N][N] per design)
+ *        u_in            : sum_d N_d * N_d complex (2 floats each) ([N][N] per design)
+ *        intensity, target, dl_di : sum_d W_d * T_d * T_d floats  ([W][T][T] per design)
+ *        loss            : n_designs doubles
+ *     dpx_plan_layout() reports each design's offsets.
+ *   - Every data pointer passed to dpx_forward / dpx_loss / dpx_backward is a caller-owned
+ *     DEVICE pointer on the current HIP device, 8-byte aligned (16-byte for fields).
+ *     The library never frees them and keeps no reference after the call returns
+ *     (except the store-mode state described at dpx_backward).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only enqueues work;
+ *     results are ready when the stream has reached that point.
+ *   - Every call returns a dpx_status; no exception crosses this interface.  On failure
+ *     dpx_last_error() gives a message for the calling thread.
+ *   - The plan owns all scratch memory (allocated in dpx_plan_create, released in
+ *     dpx_plan_destroy).  dpx_forward, dpx_loss and dpx_backward allocate nothing.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef DPX_H
+#define DPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dpx_status {
+  DPX_OK = 0,
+  DPX_E_ARG = 1,          /* invalid argument: null pointer, bad shape, misaligned buffer */
+  DPX_E_UNSUPPORTED = 2,  /* valid but not built: transform length pad*N not in the table */
+  DPX_E_NOMEM = 3,        /* device allocation failed or exceeds opts.max_workspace_bytes */
+  DPX_E_DEVICE = 4,       /* a HIP runtime error (launch failure, earlier async fault) */
+  DPX_E_STATE = 5         /* call order: store-mode backward without a matching forward */
+} dpx_status;
+
+/* One independent design (paper Section 2: K layers of N x N features, N_w wavelengths,
+ * each paired with one target image on a shared output field of view).  Host memory; the
+ * arrays are copied by dpx_plan_create. */
+typedef struct dpx_design {
+  int32_t n;         /* N: features per side of every layer (even) */
+  int32_t layers;    /* K >= 1 */
+  int32_t n_wl;      /* W >= 1 wavelengths */
+  int32_t fov;       /* F: side of the central output window, F <= N, (N - F) even */
+  int32_t bin;       /* b: detector pixel = b x b samples, F % b == 0; T = F / b */
+  int32_t pad;       /* transform length M = pad * N; 2 = zero-padded (linear convolution),
+                        1 = periodic window */
+  double dx;         /* sampling pitch (feature size), metres */
+  double n_medium;   /* refractive index of the gaps (1.0 = air) */
+  const double* wl;     /* [W] wavelengths, metres */
+  const double* n_mat;  /* [W] real refractive index n(lambda) of the layer material */
+  const double* kappa;  /* [W] extinction coefficient kappa(lambda), or NULL for 0 */
+  const double* z;      /* [K] z[l] = gap after layer l (z[K-1]: last layer -> output plane) */
+} dpx_design;
+
+typedef struct dpx_opts {
+  int32_t checkpoint_mode;  /* 0: forward stores the field after every transmission
+                               (K*W*N*N complex per design) for the backward;
+                               1: backward recomputes the forward chunk by chunk */
+  int32_t wl_chunk;         /* wavelengths per recompute chunk (0 = automatic) */
+  int32_t use_graph;        /* reserved: capture launch sequences in HIP graphs */
+  int32_t autotune;         /* reserved: time kernel variants at plan creation */
+  int32_t force_variant;    /* -1 automatic; otherwise a column-pass tile width (8 or 16) */
+  int32_t check_finite;     /* reserved */
+  int64_t max_workspace_bytes; /* 0 = no limit; otherwise plan creation fails with
+                                  DPX_E_NOMEM if the plan would need more */
+} dpx_opts;
+
+/* Offsets (in elements of the buffer's type) of one design inside the packed buffers. */
+typedef struct dpx_layout {
+  int64_t h_offset, h_count;       /* floats */
+  int64_t u_offset, u_count;       /* complex elements */
+  int64_t img_offset, img_count;   /* floats */
+  int32_t transform_len;           /* M = pad * N */
+  int32_t target_side;             /* T = fov / bin */
+  int64_t workspace_bytes;         /* device bytes the plan holds for this design */
+} dpx_layout;
+
+typedef struct dpx_plan dpx_plan;
+
+/* Fills *opts with the defaults (store mode, automatic chunking, no limit). */
+void dpx_opts_default(dpx_opts* opts);
+
+/* Validates the designs, copies their host arrays, builds the per-wavelength constant
+ * tables and twiddle tables, and allocates every device buffer the calls need on the
+ * current HIP device.  designs: [n_designs] host array; opts may be NULL (defaults).
+ * On success *out owns the plan.  Errors: DPX_E_ARG (shape rules above), DPX_E_UNSUPPORTED
+ * (pad*N not one of 64, 96, 128, 192, 256, 384, 512, 1024), DPX_E_NOMEM, DPX_E_DEVICE. */
+dpx_status dpx_plan_create(const dpx_design* designs, int32_t n_designs, const dpx_opts* opts,
+                           dpx_plan** out);
+
+/* Host-only dry run: validates like dpx_plan_create and reports the device bytes it would
+ * allocate, without touching the GPU. */
+dpx_status dpx_plan_query(const dpx_design* designs, int32_t n_designs, const dpx_opts* opts,
+                          int64_t* workspace_bytes);
+
+/* Releases the plan and its device memory (synchronises the device first). NULL is a no-op. */
+dpx_status dpx_plan_destroy(dpx_plan* plan);
+
+/* Packed-buffer offsets of design `design` (0 <= design < n_designs). */
+dpx_status dpx_plan_layout(const dpx_plan* plan, int32_t design, dpx_layout* out);
+
+/* Totals over all designs: h floats, u_in complex elements, image floats. */
+dpx_status dpx_plan_sizes(const dpx_plan* plan, int64_t* h_count, int64_t* u_count,
+                          int64_t* img_count);
+
+/* Forward pass (Eq. 1, 2, 5 and the output intensity).
+ *   h         [sum K N N] heights in metres (device, read)
+ *   u_in      [sum N N] complex input fields (device, read) or NULL for unit plane waves
+ *   intensity [sum W T T] output images (device, written)
+ * In store mode the plan also records the per-layer fields for dpx_backward. */
+dpx_status dpx_forward(dpx_plan* plan, const float* h, const float* u_in, float* intensity,
+                       void* stream);
+
+/* Loss and its gradient with respect to the intensities (see the header comment).
+ *   intensity, target [sum W T T] (device, read);  loss [n_designs] doubles (device, written);
+ *   dl_di [sum W T T] (device, written; may be NULL to skip). */
+dpx_status dpx_loss(dpx_plan* plan, const float* intensity, const float* target, double* loss,
+                    float* dl_di, void* stream);
+
+/* Backward pass: dl_dh = dL/dh given dl_di = dL/dI (Wirtinger adjoint of dpx_forward).
+ *   h, u_in as for dpx_forward;  dl_di [sum W T T] (device, read);
+ *   dl_dh [sum K N N] (device, written; summed over wavelengths in a fixed order, so the
+ *   result is bitwise reproducible).
+ * Store mode: needs the most recent dpx_forward on this plan with the same h and u_in
+ * pointers (and unchanged contents), else DPX_E_STATE.  Recompute mode: no precondition. */
+dpx_status dpx_backward(dpx_plan* plan, const float* h, const float* u_in, const float* dl_di,
+                        float* dl_dh, void* stream);
+
+/* Pass kinds reported by the per-pass timers. */
+typedef enum dpx_pass {
+  DPX_PASS_COL_FWD = 0,       /* column pass with H (forward) */
+  DPX_PASS_COL_ADJ = 1,       /* column pass with conj(H) (adjoint) */
+  DPX_PASS_ROW_FWD_FIRST = 2, /* u_in * t_0 -> row FFT */
+  DPX_PASS_ROW_FWD_MID = 3,   /* row IFFT -> crop -> * t_l -> row FFT */
+  DPX_PASS_ROW_FWD_LAST = 4,  /* row IFFT -> output field of view */
+  DPX_PASS_ROW_ADJ_SEED = 5,  /* 2 dL/dI o -> row FFT */
+  DPX_PASS_ROW_ADJ_MID = 6,   /* row IFFT -> dL/dh partial -> * conj(t_l) -> row FFT */
+  DPX_PASS_ROW_ADJ_LAST = 7,  /* row IFFT -> dL/dh partial (first layer) */
+  DPX_PASS_COUNT = 8
+} dpx_pass;
+
+/* Per-pass timers (measurement support).  While enabled, every launch of the passes above is
+ * bracketed by a pair of HIP events recorded on the call's stream, and the launch's
+ * algorithmic device-memory traffic (bytes the pass must read and write once) is counted.
+ * Enabling or disabling clears the counters. */
+dpx_status dpx_timing_enable(dpx_plan* plan, int32_t enable);
+
+/* Waits for the recorded events and returns, for pass `pass`, the summed kernel time in
+ * milliseconds, the number of launches and the summed algorithmic bytes since the timers
+ * were enabled.  Any output pointer may be NULL. */
+dpx_status dpx_timing_read(dpx_plan* plan, int32_t pass, double* total_ms, int64_t* launches,
+                           int64_t* bytes);
+
+/* Message for the last failed call on this thread ("" if none).  Valid until the next call
+ * on this thread. */
+const char* dpx_last_error(void);
+
+/* Library version string. */
+const char* dpx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPX_H */

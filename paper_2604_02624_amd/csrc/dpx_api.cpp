@@ -1,0 +1,656 @@
+// C ABI of the dpx library: plan creation (validation, per-wavelength constants, twiddle
+// tables, workspace), and the forward / loss / backward call sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dpx.h"
+#include "dpx_internal.hpp"
+
+using dpx::ColArgs;
+using dpx::RowArgs;
+using dpx::WlConst;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dpx_status fail(dpx_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+dpx_status ok() {
+  g_last_error.clear();
+  return DPX_OK;
+}
+
+#define DPX_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(DPX_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
+  } while (0)
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+struct Design {
+  int N, M, K, W, F, b, T, pad;
+  double dx, n_m;
+  std::vector<double> wl, n_mat, kappa, z;
+  int64_t h_off, u_off, img_off;
+  // launch geometry
+  int wl_chunk;      // wavelengths per chunk (spec buffer depth)
+  int w_per_block;   // wavelengths per row-pass block
+  int nslots;        // dL/dh partial slots = ceil(wl_chunk / w_per_block)
+  int row_group;     // rows per row-pass block
+  int col_tx;        // columns per column-pass block
+  // device memory
+  WlConst* d_wl = nullptr;
+  float2* spec = nullptr;
+  float2* ckpt = nullptr;
+  float2* ofov = nullptr;
+  float* dh_part = nullptr;
+  double* per_wl = nullptr;
+  int64_t bytes = 0;
+};
+
+}  // namespace
+
+struct TimedLaunch {
+  int pass;
+  hipEvent_t start, stop;
+  int64_t bytes;
+};
+
+struct PassTotals {
+  double ms = 0.0;
+  int64_t launches = 0;
+  int64_t bytes = 0;
+};
+
+struct dpx_plan {
+  std::vector<Design> designs;
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  PassTotals totals[DPX_PASS_COUNT];
+  dpx_opts opts;
+  int device = 0;
+  std::map<int, float2*> twiddles;
+  int64_t bytes = 0;
+  bool fwd_valid = false;
+  const float* last_h = nullptr;
+  const float* last_u = nullptr;
+};
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
+  if (!ds) return fail(DPX_E_ARG, "designs is NULL");
+  if (nd < 1) return fail(DPX_E_ARG, "n_designs must be >= 1 (got %d)", nd);
+  if (o) {
+    if (o->checkpoint_mode != 0 && o->checkpoint_mode != 1)
+      return fail(DPX_E_ARG, "checkpoint_mode must be 0 or 1");
+    if (o->wl_chunk < 0) return fail(DPX_E_ARG, "wl_chunk must be >= 0");
+    if (o->max_workspace_bytes < 0) return fail(DPX_E_ARG, "max_workspace_bytes must be >= 0");
+    if (o->force_variant != -1 && o->force_variant != 0 && o->force_variant != 8 &&
+        o->force_variant != 16)
+      return fail(DPX_E_ARG, "force_variant must be -1, 8 or 16");
+  }
+  for (int i = 0; i < nd; ++i) {
+    const dpx_design& d = ds[i];
+    if (d.n < 2 || d.n % 2) return fail(DPX_E_ARG, "design %d: n must be even and >= 2 (got %d)", i, d.n);
+    if (d.layers < 1) return fail(DPX_E_ARG, "design %d: layers must be >= 1", i);
+    if (d.n_wl < 1) return fail(DPX_E_ARG, "design %d: n_wl must be >= 1", i);
+    if (d.fov < 1 || d.fov > d.n || (d.n - d.fov) % 2)
+      return fail(DPX_E_ARG, "design %d: fov must be in [1, n] with n - fov even (n=%d fov=%d)", i,
+                  d.n, d.fov);
+    if (d.bin < 1 || d.fov % d.bin) return fail(DPX_E_ARG, "design %d: fov %% bin must be 0", i);
+    if (d.pad != 1 && d.pad != 2) return fail(DPX_E_ARG, "design %d: pad must be 1 or 2", i);
+    if (!finite_pos(d.dx)) return fail(DPX_E_ARG, "design %d: dx must be finite and > 0", i);
+    if (!finite_pos(d.n_medium)) return fail(DPX_E_ARG, "design %d: n_medium must be > 0", i);
+    if (!d.wl || !d.n_mat || !d.z) return fail(DPX_E_ARG, "design %d: wl, n_mat and z are required", i);
+    for (int w = 0; w < d.n_wl; ++w) {
+      if (!finite_pos(d.wl[w])) return fail(DPX_E_ARG, "design %d: wl[%d] must be > 0", i, w);
+      if (!std::isfinite(d.n_mat[w])) return fail(DPX_E_ARG, "design %d: n_mat[%d] not finite", i, w);
+      if (d.kappa && !(std::isfinite(d.kappa[w]) && d.kappa[w] >= 0.0))
+        return fail(DPX_E_ARG, "design %d: kappa[%d] must be finite and >= 0", i, w);
+    }
+    for (int l = 0; l < d.layers; ++l)
+      if (!(std::isfinite(d.z[l]) && d.z[l] >= 0.0))
+        return fail(DPX_E_ARG, "design %d: z[%d] must be finite and >= 0", i, l);
+    const int M = d.pad * d.n;
+    if (!dpx::fft_size_supported(M))
+      return fail(DPX_E_UNSUPPORTED,
+                  "design %d: transform length pad*n = %d is not built (64, 96, 128, 192, 256, "
+                  "384, 512, 1024)",
+                  i, M);
+  }
+  return DPX_OK;
+}
+
+// Geometry and byte counts for one design (host only).
+void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
+  d.N = src.n;
+  d.pad = src.pad;
+  d.M = src.pad * src.n;
+  d.K = src.layers;
+  d.W = src.n_wl;
+  d.F = src.fov;
+  d.b = src.bin;
+  d.T = src.fov / src.bin;
+  d.dx = src.dx;
+  d.n_m = src.n_medium;
+  const int P = dpx::row_lanes_per_transform(d.M);
+  d.row_group = 256 / P;
+  const int row_blocks = (d.N + d.row_group - 1) / d.row_group;
+  // wavelengths per chunk: everything at once unless asked otherwise (recompute mode
+  // defaults to chunks of 64)
+  int chunk = o.wl_chunk > 0 ? o.wl_chunk : (o.checkpoint_mode == 1 ? 64 : d.W);
+  chunk = std::min(chunk, d.W);
+  // wavelengths per row-pass block: enough blocks to fill the chip (about 2048), at most 16
+  int wpb = static_cast<int>(std::max<int64_t>(1, static_cast<int64_t>(chunk) * row_blocks / 2048));
+  wpb = std::min(wpb, 16);
+  if (chunk < d.W) {
+    // chunks must hold whole blocks so every chunk maps onto the same partial slots
+    chunk = std::max(wpb, chunk / wpb * wpb);
+  }
+  d.wl_chunk = chunk;
+  d.w_per_block = wpb;
+  d.nslots = (chunk + wpb - 1) / wpb;
+  // 16-column tiles give 128-byte row segments; at M = 1024 their 1024-thread blocks cap the
+  // registers at 128 per lane, so 8-column tiles are the default there
+  d.col_tx = (o.force_variant == 8 || o.force_variant == 16) ? o.force_variant : (d.M >= 1024 ? 8 : 16);
+  const int64_t nn = static_cast<int64_t>(d.N) * d.N;
+  const int ck_w = (o.checkpoint_mode == 1) ? chunk : d.W;
+  const int of_w = (o.checkpoint_mode == 1) ? chunk : d.W;
+  d.bytes = static_cast<int64_t>(chunk) * d.N * d.M * 8      // spec
+            + static_cast<int64_t>(d.K) * ck_w * nn * 8       // checkpoints
+            + static_cast<int64_t>(of_w) * d.F * d.F * 8      // output field
+            + static_cast<int64_t>(d.nslots) * d.K * nn * 4   // dL/dh partials
+            + static_cast<int64_t>(d.W) * 8                   // per-wavelength loss
+            + static_cast<int64_t>(d.W) * sizeof(WlConst);
+}
+
+void free_design(Design& d) {
+  hipFree(d.d_wl);
+  hipFree(d.spec);
+  hipFree(d.ckpt);
+  hipFree(d.ofov);
+  hipFree(d.dh_part);
+  hipFree(d.per_wl);
+  d.d_wl = nullptr;
+  d.spec = d.ckpt = d.ofov = nullptr;
+  d.dh_part = nullptr;
+  d.per_wl = nullptr;
+}
+
+template <typename T>
+dpx_status dev_alloc(T** p, int64_t bytes, const char* what) {
+  if (bytes <= 0) {
+    *p = nullptr;
+    return DPX_OK;
+  }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), static_cast<size_t>(bytes));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(DPX_E_NOMEM, "hipMalloc of %lld bytes for %s failed: %s", static_cast<long long>(bytes),
+                what, hipGetErrorString(e));
+  }
+  return DPX_OK;
+}
+
+dpx_status check_ptr(const void* p, size_t align, const char* name) {
+  if (!p) return fail(DPX_E_ARG, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(p) % align)
+    return fail(DPX_E_ARG, "%s is not %zu-byte aligned", name, align);
+  return DPX_OK;
+}
+
+dpx_status sticky_check() {
+  hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DPX_E_DEVICE, "pending HIP error: %s", hipGetErrorString(e));
+  }
+  return DPX_OK;
+}
+
+#define DPX_TRY(expr)                   \
+  do {                                  \
+    dpx_status s_ = (expr);             \
+    if (s_ != DPX_OK) return s_;        \
+  } while (0)
+
+RowArgs row_args(const dpx_plan* p, const Design& d, int w0, int wc) {
+  RowArgs a{};
+  a.wl = d.d_wl;
+  a.tw = p->twiddles.at(d.M);
+  a.n = d.N;
+  a.fov = d.F;
+  a.bin = d.b;
+  a.layers = d.K;
+  a.w_begin = w0;
+  a.w_count = wc;
+  a.w_per_block = d.w_per_block;
+  a.chunk_base = 0;
+  a.spec = d.spec;
+  const int64_t nn = static_cast<int64_t>(d.N) * d.N;
+  if (p->opts.checkpoint_mode == 1) {
+    a.ckpt = d.ckpt;
+    a.ckpt_w_stride = d.wl_chunk;
+    a.ofov = d.ofov;
+  } else {
+    a.ckpt = d.ckpt + w0 * nn;
+    a.ckpt_w_stride = d.W;
+    a.ofov = d.ofov + static_cast<int64_t>(w0) * d.F * d.F;
+  }
+  a.dh_part = d.dh_part;
+  return a;
+}
+
+dpx_status timer_begin(dpx_plan* p, hipStream_t s, TimedLaunch& t) {
+  if (!p->timing) return DPX_OK;
+  DPX_HIP(hipEventCreate(&t.start));
+  DPX_HIP(hipEventCreate(&t.stop));
+  DPX_HIP(hipEventRecord(t.start, s));
+  return DPX_OK;
+}
+
+dpx_status timer_end(dpx_plan* p, hipStream_t s, TimedLaunch& t) {
+  if (!p->timing) return DPX_OK;
+  DPX_HIP(hipEventRecord(t.stop, s));
+  p->pending.push_back(t);
+  return DPX_OK;
+}
+
+// algorithmic bytes of one row-pass launch (every operand read or written once)
+int64_t row_bytes(const Design& d, int mode, int wc, int nwb, bool accumulate, bool has_u) {
+  const int64_t nn = static_cast<int64_t>(d.N) * d.N;
+  const int64_t row = static_cast<int64_t>(d.M) * 8;  // one spectrum row
+  const int64_t fov = static_cast<int64_t>(d.F) * d.F * 8;
+  const int64_t part = nwb * nn * 4 * (accumulate ? 2 : 1);
+  switch (mode) {
+    case dpx::ROW_FWD_FIRST: return wc * (d.N * row + 8 * nn) + 4 * nn + (has_u ? 8 * nn : 0);
+    case dpx::ROW_FWD_MID: return wc * (2 * d.N * row + 8 * nn) + 4 * nn;
+    case dpx::ROW_FWD_LAST: return wc * (d.F * row + fov);
+    case dpx::ROW_ADJ_SEED: return wc * (fov + 4 * d.T * d.T + d.F * row);
+    case dpx::ROW_ADJ_MID: return wc * (2 * d.N * row + 8 * nn) + 4 * nn + part;
+    case dpx::ROW_ADJ_LAST: return wc * (d.N * row + 8 * nn) + 4 * nn + part;
+    default: return 0;
+  }
+}
+
+dpx_status run_row(dpx_plan* p, const Design& d, int mode, RowArgs a, int row_lo, int row_hi, hipStream_t s) {
+  a.row_lo = row_lo;
+  a.row_hi = row_hi;
+  const int nrb = (row_hi - row_lo + d.row_group - 1) / d.row_group;
+  const int nwb = (a.w_count + d.w_per_block - 1) / d.w_per_block;
+  TimedLaunch t{DPX_PASS_ROW_FWD_FIRST + mode, nullptr, nullptr,
+                row_bytes(d, mode, a.w_count, nwb, a.accumulate != 0, a.u_in != nullptr)};
+  DPX_TRY(timer_begin(p, s, t));
+  hipError_t e = dpx::launch_row(d.M, d.pad, mode, a, nrb, nwb, s);
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "row pass (mode %d) launch failed: %s", mode, hipGetErrorString(e));
+  DPX_TRY(timer_end(p, s, t));
+  return DPX_OK;
+}
+
+dpx_status run_col(dpx_plan* p, const Design& d, int layer, bool conj, int w0, int wc,
+                   int in_lo, int in_hi, int out_lo, int out_hi, hipStream_t s) {
+  ColArgs c{};
+  c.spec = d.spec;
+  c.wl = d.d_wl;
+  c.tw = p->twiddles.at(d.M);
+  c.zrev = d.z[layer] / (static_cast<double>(d.M) * d.dx);
+  c.n = d.N;
+  c.in_lo = in_lo;
+  c.in_hi = in_hi;
+  c.out_lo = out_lo;
+  c.out_hi = out_hi;
+  c.w_begin = w0;
+  TimedLaunch t{conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD, nullptr, nullptr,
+                static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo))};
+  DPX_TRY(timer_begin(p, s, t));
+  hipError_t e = dpx::launch_col(d.M, d.pad, conj, d.col_tx, c, wc, s);
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "column pass launch failed: %s", hipGetErrorString(e));
+  DPX_TRY(timer_end(p, s, t));
+  return DPX_OK;
+}
+
+int64_t h_off_layer(const Design& d, int l) { return d.h_off + static_cast<int64_t>(l) * d.N * d.N; }
+
+// forward over one chunk of wavelengths [w0, w0 + wc); leaves the output field in ofov
+dpx_status forward_chunk(dpx_plan* p, const Design& d, const float* h, const float* u_in,
+                         int w0, int wc, hipStream_t s) {
+  const int fo = (d.N - d.F) / 2;
+  RowArgs a = row_args(p, d, w0, wc);
+  a.u_in = u_in ? reinterpret_cast<const float2*>(u_in) + d.u_off : nullptr;
+  a.store_ckpt = 1;
+  a.layer = 0;
+  a.h = h + h_off_layer(d, 0);
+  DPX_TRY(run_row(p, d, dpx::ROW_FWD_FIRST, a, 0, d.N, s));
+  for (int l = 0; l < d.K; ++l) {
+    const bool last = (l == d.K - 1);
+    DPX_TRY(run_col(p, d, l, false, w0, wc, 0, d.N, last ? fo : 0, last ? fo + d.F : d.N, s));
+    if (!last) {
+      a.layer = l + 1;
+      a.h = h + h_off_layer(d, l + 1);
+      DPX_TRY(run_row(p, d, dpx::ROW_FWD_MID, a, 0, d.N, s));
+    } else {
+      DPX_TRY(run_row(p, d, dpx::ROW_FWD_LAST, a, fo, fo + d.F, s));
+    }
+  }
+  return DPX_OK;
+}
+
+dpx_status adjoint_chunk(dpx_plan* p, const Design& d, const float* h, const float* dl_di,
+                         int w0, int wc, bool accumulate_first, hipStream_t s) {
+  const int fo = (d.N - d.F) / 2;
+  RowArgs a = row_args(p, d, w0, wc);
+  a.dl_di = dl_di + d.img_off;
+  a.store_ckpt = 0;
+  a.accumulate = accumulate_first ? 1 : 0;
+  DPX_TRY(run_row(p, d, dpx::ROW_ADJ_SEED, a, fo, fo + d.F, s));
+  for (int l = d.K - 1; l >= 0; --l) {
+    const bool first = (l == d.K - 1);
+    DPX_TRY(run_col(p, d, l, true, w0, wc, first ? fo : 0, first ? fo + d.F : d.N, 0, d.N, s));
+    a.layer = l;
+    a.h = h + h_off_layer(d, l);
+    DPX_TRY(run_row(p, d, l > 0 ? dpx::ROW_ADJ_MID : dpx::ROW_ADJ_LAST, a, 0, d.N, s));
+  }
+  return DPX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dpx_opts_default(dpx_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->checkpoint_mode = 0;
+  o->wl_chunk = 0;
+  o->use_graph = 0;
+  o->autotune = 0;
+  o->force_variant = -1;
+  o->check_finite = 0;
+  o->max_workspace_bytes = 0;
+}
+
+const char* dpx_last_error(void) { return g_last_error.c_str(); }
+
+const char* dpx_version(void) { return "dpx 0.1 (gfx950)"; }
+
+dpx_status dpx_plan_query(const dpx_design* ds, int32_t nd, const dpx_opts* opts, int64_t* bytes) {
+  dpx_opts o;
+  dpx_opts_default(&o);
+  if (opts) o = *opts;
+  DPX_TRY(validate(ds, nd, opts ? &o : nullptr));
+  if (!bytes) return fail(DPX_E_ARG, "workspace_bytes is NULL");
+  int64_t tot = 0;
+  std::map<int, int> ms;
+  for (int i = 0; i < nd; ++i) {
+    Design d;
+    layout_design(ds[i], o, d);
+    tot += d.bytes;
+    ms[d.M] = 1;
+  }
+  for (auto& kv : ms) tot += static_cast<int64_t>(kv.first) * 8;
+  *bytes = tot;
+  return ok();
+}
+
+dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opts, dpx_plan** out) {
+  if (!out) return fail(DPX_E_ARG, "out is NULL");
+  *out = nullptr;
+  dpx_opts o;
+  dpx_opts_default(&o);
+  if (opts) o = *opts;
+  DPX_TRY(validate(ds, nd, &o));
+  int64_t need = 0;
+  DPX_TRY(dpx_plan_query(ds, nd, &o, &need));
+  if (o.max_workspace_bytes > 0 && need > o.max_workspace_bytes)
+    return fail(DPX_E_NOMEM, "plan needs %lld device bytes, limit is %lld", static_cast<long long>(need),
+                static_cast<long long>(o.max_workspace_bytes));
+
+  dpx_plan* p = new dpx_plan();
+  p->opts = o;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(DPX_E_DEVICE, "no HIP device");
+  }
+  int64_t h_off = 0, u_off = 0, img_off = 0;
+  p->designs.resize(nd);
+  dpx_status st = DPX_OK;
+  for (int i = 0; i < nd && st == DPX_OK; ++i) {
+    const dpx_design& src = ds[i];
+    Design& d = p->designs[i];
+    layout_design(src, o, d);
+    d.wl.assign(src.wl, src.wl + src.n_wl);
+    d.n_mat.assign(src.n_mat, src.n_mat + src.n_wl);
+    d.kappa.assign(src.n_wl, 0.0);
+    if (src.kappa) d.kappa.assign(src.kappa, src.kappa + src.n_wl);
+    d.z.assign(src.z, src.z + src.layers);
+    d.h_off = h_off;
+    d.u_off = u_off;
+    d.img_off = img_off;
+    h_off += static_cast<int64_t>(d.K) * d.N * d.N;
+    u_off += static_cast<int64_t>(d.N) * d.N;
+    img_off += static_cast<int64_t>(d.W) * d.T * d.T;
+    // per-wavelength constants (double precision on the host)
+    std::vector<WlConst> tab(d.W);
+    const double md = static_cast<double>(d.M) * d.dx;
+    for (int w = 0; w < d.W; ++w) {
+      const double lam = d.wl[w];
+      tab[w].rt = (d.n_mat[w] - d.n_m) / lam;
+      tab[w].ca = kTwoPi * d.kappa[w] / lam;
+      const double r = md * d.n_m / lam;
+      tab[w].q0 = r * r;
+      tab[w].ct = kTwoPi * (d.n_mat[w] - d.n_m) / lam;
+    }
+    const int64_t nn = static_cast<int64_t>(d.N) * d.N;
+    const int ck_w = (o.checkpoint_mode == 1) ? d.wl_chunk : d.W;
+    if ((st = dev_alloc(&d.d_wl, d.W * sizeof(WlConst), "wavelength table")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.spec, static_cast<int64_t>(d.wl_chunk) * d.N * d.M * 8, "spectra")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.ckpt, static_cast<int64_t>(d.K) * ck_w * nn * 8, "checkpoints")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.ofov, static_cast<int64_t>(ck_w) * d.F * d.F * 8, "output field")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.dh_part, static_cast<int64_t>(d.nslots) * d.K * nn * 4, "gradient partials")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.per_wl, d.W * 8, "per-wavelength loss")) != DPX_OK) break;
+    if (hipMemcpy(d.d_wl, tab.data(), d.W * sizeof(WlConst), hipMemcpyHostToDevice) != hipSuccess) {
+      st = fail(DPX_E_DEVICE, "copy of the wavelength table failed");
+      break;
+    }
+    p->bytes += d.bytes;
+    if (!p->twiddles.count(d.M)) {
+      std::vector<float2> tw(d.M);
+      for (int m = 0; m < d.M; ++m) {
+        const double ang = kTwoPi * static_cast<double>(m) / static_cast<double>(d.M);
+        tw[m] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(-std::sin(ang)));
+      }
+      float2* dtw = nullptr;
+      if ((st = dev_alloc(&dtw, static_cast<int64_t>(d.M) * 8, "twiddles")) != DPX_OK) break;
+      p->twiddles[d.M] = dtw;
+      if (hipMemcpy(dtw, tw.data(), d.M * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        st = fail(DPX_E_DEVICE, "copy of the twiddle table failed");
+        break;
+      }
+      p->bytes += static_cast<int64_t>(d.M) * 8;
+    }
+  }
+  if (st != DPX_OK) {
+    std::string msg = g_last_error;
+    dpx_plan_destroy(p);
+    g_last_error = msg;
+    return st;
+  }
+  *out = p;
+  return ok();
+}
+
+dpx_status dpx_plan_destroy(dpx_plan* p) {
+  if (!p) return ok();
+  (void)hipDeviceSynchronize();
+  for (auto& t : p->pending) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (auto& d : p->designs) free_design(d);
+  for (auto& kv : p->twiddles) hipFree(kv.second);
+  delete p;
+  return ok();
+}
+
+dpx_status dpx_plan_layout(const dpx_plan* p, int32_t i, dpx_layout* out) {
+  if (!p || !out) return fail(DPX_E_ARG, "plan and out must not be NULL");
+  if (i < 0 || i >= static_cast<int>(p->designs.size()))
+    return fail(DPX_E_ARG, "design index %d out of range", i);
+  const Design& d = p->designs[i];
+  out->h_offset = d.h_off;
+  out->h_count = static_cast<int64_t>(d.K) * d.N * d.N;
+  out->u_offset = d.u_off;
+  out->u_count = static_cast<int64_t>(d.N) * d.N;
+  out->img_offset = d.img_off;
+  out->img_count = static_cast<int64_t>(d.W) * d.T * d.T;
+  out->transform_len = d.M;
+  out->target_side = d.T;
+  out->workspace_bytes = d.bytes;
+  return ok();
+}
+
+dpx_status dpx_plan_sizes(const dpx_plan* p, int64_t* h_count, int64_t* u_count, int64_t* img_count) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  int64_t hc = 0, uc = 0, ic = 0;
+  for (const auto& d : p->designs) {
+    hc += static_cast<int64_t>(d.K) * d.N * d.N;
+    uc += static_cast<int64_t>(d.N) * d.N;
+    ic += static_cast<int64_t>(d.W) * d.T * d.T;
+  }
+  if (h_count) *h_count = hc;
+  if (u_count) *u_count = uc;
+  if (img_count) *img_count = ic;
+  return ok();
+}
+
+dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* intensity, void* stream) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  DPX_TRY(check_ptr(h, 4, "h"));
+  DPX_TRY(check_ptr(intensity, 4, "intensity"));
+  if (u_in) DPX_TRY(check_ptr(u_in, 8, "u_in"));
+  DPX_TRY(sticky_check());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  p->fwd_valid = false;
+  for (const auto& d : p->designs) {
+    for (int w0 = 0; w0 < d.W; w0 += d.wl_chunk) {
+      const int wc = std::min(d.wl_chunk, d.W - w0);
+      DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, s));
+      const float2* of = (p->opts.checkpoint_mode == 1) ? d.ofov : d.ofov + static_cast<int64_t>(w0) * d.F * d.F;
+      hipError_t e = dpx::launch_bin_intensity(of, intensity + d.img_off + static_cast<int64_t>(w0) * d.T * d.T,
+                                               wc, d.F, d.b, s);
+      if (e != hipSuccess) return fail(DPX_E_DEVICE, "intensity launch failed: %s", hipGetErrorString(e));
+    }
+  }
+  p->fwd_valid = (p->opts.checkpoint_mode == 0);
+  p->last_h = h;
+  p->last_u = u_in;
+  return ok();
+}
+
+dpx_status dpx_loss(dpx_plan* p, const float* intensity, const float* target, double* loss, float* dl_di,
+                    void* stream) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  DPX_TRY(check_ptr(intensity, 4, "intensity"));
+  DPX_TRY(check_ptr(target, 4, "target"));
+  DPX_TRY(check_ptr(loss, 8, "loss"));
+  if (dl_di) DPX_TRY(check_ptr(dl_di, 4, "dl_di"));
+  DPX_TRY(sticky_check());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (size_t i = 0; i < p->designs.size(); ++i) {
+    const Design& d = p->designs[i];
+    hipError_t e = dpx::launch_loss(intensity + d.img_off, target + d.img_off, dl_di ? dl_di + d.img_off : nullptr,
+                                    d.per_wl, d.W, d.T, s);
+    if (e == hipSuccess) e = dpx::launch_loss_sum(d.per_wl, loss + i, d.W, s);
+    if (e != hipSuccess) return fail(DPX_E_DEVICE, "loss launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const float* dl_di, float* dl_dh,
+                        void* stream) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  DPX_TRY(check_ptr(h, 4, "h"));
+  DPX_TRY(check_ptr(dl_di, 4, "dl_di"));
+  DPX_TRY(check_ptr(dl_dh, 4, "dl_dh"));
+  if (u_in) DPX_TRY(check_ptr(u_in, 8, "u_in"));
+  DPX_TRY(sticky_check());
+  const bool store = (p->opts.checkpoint_mode == 0);
+  if (store && !(p->fwd_valid && p->last_h == h && p->last_u == u_in))
+    return fail(DPX_E_STATE,
+                "store-mode backward needs a preceding dpx_forward on this plan with the same h and "
+                "u_in");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (const auto& d : p->designs) {
+    int chunk_i = 0;
+    for (int w0 = 0; w0 < d.W; w0 += d.wl_chunk, ++chunk_i) {
+      const int wc = std::min(d.wl_chunk, d.W - w0);
+      if (!store) DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, s));
+      DPX_TRY(adjoint_chunk(p, d, h, dl_di, w0, wc, chunk_i > 0, s));
+    }
+    (void)chunk_i;
+    const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;
+    hipError_t e = dpx::launch_dh_reduce(d.dh_part, dl_dh + d.h_off, d.nslots, per, s);
+    if (e != hipSuccess) return fail(DPX_E_DEVICE, "gradient reduction launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+dpx_status dpx_timing_enable(dpx_plan* p, int32_t enable) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  for (auto& t : p->pending) {
+    (void)hipEventSynchronize(t.stop);
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  p->pending.clear();
+  for (auto& t : p->totals) t = PassTotals{};
+  p->timing = enable != 0;
+  return ok();
+}
+
+dpx_status dpx_timing_read(dpx_plan* p, int32_t pass, double* total_ms, int64_t* launches, int64_t* bytes) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  if (pass < 0 || pass >= DPX_PASS_COUNT) return fail(DPX_E_ARG, "pass %d out of range", pass);
+  for (auto& t : p->pending) {
+    DPX_HIP(hipEventSynchronize(t.stop));
+    float ms = 0.f;
+    DPX_HIP(hipEventElapsedTime(&ms, t.start, t.stop));
+    PassTotals& a = p->totals[t.pass];
+    a.ms += ms;
+    a.launches += 1;
+    a.bytes += t.bytes;
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  p->pending.clear();
+  const PassTotals& a = p->totals[pass];
+  if (total_ms) *total_ms = a.ms;
+  if (launches) *launches = a.launches;
+  if (bytes) *bytes = a.bytes;
+  return ok();
+}
+
+}  // extern "C"

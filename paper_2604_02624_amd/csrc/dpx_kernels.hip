@@ -1,0 +1,507 @@
+// HIP kernels for gfx950: row passes, column passes, intensity binning, loss, reductions.
+//
+// One propagation over a gap (Section 4, Eq. 4/5 via the angular spectrum) is split in two
+// passes over a [N rows][M columns] complex plane per wavelength ("spec"):
+//   row pass    : transform along x (the N non-zero rows of the zero-padded plane only)
+//   column pass : transform along y, multiply by the transfer function, inverse along y,
+//                 keep the N aperture rows
+// and the next row pass starts with the inverse transform along x.  Zero padding is placed
+// at the high end of each axis instead of centring it: a circular convolution commutes with
+// shifts, so cropping the same corner returns the same N x N field.
+#include "dpx_internal.hpp"
+#include "fft.hpp"
+
+namespace dpx {
+
+// exp(+i 2 pi rev), with rev reduced to [-1/2, 1/2] in double precision first
+__device__ __forceinline__ float2 cis_rev(double rev) {
+  const double f = rev - rint(rev);
+  float s, c;
+  sincospif(2.0f * static_cast<float>(f), &s, &c);
+  return make_float2(c, s);
+}
+
+// Eq. 1 with the +j reading: t = exp(-ca h) exp(+i 2 pi rt h); phase argument in double.
+__device__ __forceinline__ float2 transmission(float h, const WlConst& c) {
+  const double hd = static_cast<double>(h);
+  float2 t = cis_rev(c.rt * hd);
+  if (c.ca != 0.0) {
+    const float a = expf(-static_cast<float>(c.ca * hd));
+    t.x *= a;
+    t.y *= a;
+  }
+  return t;
+}
+
+constexpr int kRowThreads = 256;
+
+// ------------------------------------------------------------------------------------------
+// Row pass.  A block owns G = 256 / P consecutive rows (one transform group per row) and
+// loops over a run of wavelengths, so the row's heights stay in registers.
+// ------------------------------------------------------------------------------------------
+template <int M, int PAD, int MODE>
+__global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
+  constexpr int E = Geo<M>::E;
+  constexpr int P = Geo<M>::P;
+  constexpr int G = kRowThreads / P;
+  constexpr int EN = E / PAD;  // registers that hold x < N
+  constexpr bool HALF = (PAD == 2);
+  __shared__ float2 lds_all[G * M];
+
+  const int N = M / PAD;
+  const int g = threadIdx.x / P;
+  const int j0 = threadIdx.x % P;
+  float2* lds = lds_all + g * M;
+  const int y_raw = a.row_lo + blockIdx.x * G + g;
+  const bool active = y_raw < a.row_hi;
+  const int y = active ? y_raw : a.row_lo;
+  const size_t plane = static_cast<size_t>(N) * M;
+  const size_t nn = static_cast<size_t>(N) * N;
+
+  const int wb = a.w_begin + blockIdx.y * a.w_per_block;
+  const int we = min(wb + a.w_per_block, a.w_begin + a.w_count);
+
+  float hreg[EN];
+  if constexpr (MODE == ROW_FWD_FIRST || MODE == ROW_FWD_MID || MODE == ROW_ADJ_MID ||
+                MODE == ROW_ADJ_LAST) {
+#pragma unroll
+    for (int t = 0; t < EN; ++t) hreg[t] = a.h[static_cast<size_t>(y) * N + j0 + P * t];
+  }
+
+  if constexpr (MODE == ROW_FWD_FIRST) {
+    float2 uin[EN];
+#pragma unroll
+    for (int t = 0; t < EN; ++t)
+      uin[t] = a.u_in ? a.u_in[static_cast<size_t>(y) * N + j0 + P * t] : make_float2(1.f, 0.f);
+    for (int w = wb; w < we; ++w) {
+      const WlConst c = a.wl[w];
+      const int wc = w - a.w_begin;
+      float2 reg[E];
+#pragma unroll
+      for (int t = 0; t < EN; ++t) reg[t] = cmul(uin[t], transmission(hreg[t], c));
+      if (a.store_ckpt && active) {
+        float2* ck = a.ckpt + (static_cast<size_t>(a.layer) * a.ckpt_w_stride + wc) * nn +
+                     static_cast<size_t>(y) * N;
+#pragma unroll
+        for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
+      }
+      fft<M, false, HALF>(reg, lds, j0, a.tw);
+      if (active) {
+        float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
+#pragma unroll
+        for (int t = 0; t < E; ++t) dst[j0 + P * t] = reg[t];
+      }
+    }
+  } else if constexpr (MODE == ROW_FWD_MID) {
+    for (int w = wb; w < we; ++w) {
+      const WlConst c = a.wl[w];
+      const int wc = w - a.w_begin;
+      float2* row = a.spec + wc * plane + static_cast<size_t>(y) * M;
+      float2 reg[E];
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
+      fft<M, true, false>(reg, lds, j0, a.tw);
+#pragma unroll
+      for (int t = 0; t < EN; ++t) reg[t] = cmul(reg[t], transmission(hreg[t], c));
+      if (a.store_ckpt && active) {
+        float2* ck = a.ckpt + (static_cast<size_t>(a.layer) * a.ckpt_w_stride + wc) * nn +
+                     static_cast<size_t>(y) * N;
+#pragma unroll
+        for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
+      }
+      fft<M, false, HALF>(reg, lds, j0, a.tw);
+      if (active) {
+#pragma unroll
+        for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
+      }
+    }
+  } else if constexpr (MODE == ROW_FWD_LAST) {
+    const int F = a.fov;
+    const int x0 = (N - F) / 2;
+    for (int w = wb; w < we; ++w) {
+      const int wc = w - a.w_begin;
+      const float2* row = a.spec + wc * plane + static_cast<size_t>(y) * M;
+      float2 reg[E];
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
+      fft<M, true, false>(reg, lds, j0, a.tw);
+      if (active) {
+        float2* dst = a.ofov + static_cast<size_t>(wc) * F * F + static_cast<size_t>(y - x0) * F;
+#pragma unroll
+        for (int t = 0; t < EN; ++t) {
+          const int x = j0 + P * t;
+          if (x >= x0 && x < x0 + F) dst[x - x0] = reg[t];
+        }
+      }
+    }
+  } else if constexpr (MODE == ROW_ADJ_SEED) {
+    const int F = a.fov, b = a.bin, T = F / b;
+    const int x0 = (N - F) / 2;
+    for (int w = wb; w < we; ++w) {
+      const int wc = w - a.w_begin;
+      const float2* o = a.ofov + static_cast<size_t>(wc) * F * F + static_cast<size_t>(y - x0) * F;
+      const float* d = a.dl_di + static_cast<size_t>(w) * T * T + static_cast<size_t>((y - x0) / b) * T;
+      float2 reg[E];
+#pragma unroll
+      for (int t = 0; t < EN; ++t) {
+        const int x = j0 + P * t;
+        if (x >= x0 && x < x0 + F) {
+          const float s = 2.0f * d[(x - x0) / b];
+          reg[t] = cscale(o[x - x0], s);
+        } else {
+          reg[t] = make_float2(0.f, 0.f);
+        }
+      }
+      fft<M, false, HALF>(reg, lds, j0, a.tw);
+      if (active) {
+        float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
+#pragma unroll
+        for (int t = 0; t < E; ++t) dst[j0 + P * t] = reg[t];
+      }
+    }
+  } else {  // ROW_ADJ_MID, ROW_ADJ_LAST
+    float acc[EN];
+#pragma unroll
+    for (int t = 0; t < EN; ++t) acc[t] = 0.f;
+    for (int w = wb; w < we; ++w) {
+      const WlConst c = a.wl[w];
+      const int wc = w - a.w_begin;
+      float2* row = a.spec + wc * plane + static_cast<size_t>(y) * M;
+      const float2* ck = a.ckpt + (static_cast<size_t>(a.layer) * a.ckpt_w_stride + wc) * nn +
+                         static_cast<size_t>(y) * N;
+      float2 reg[E];
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
+      fft<M, true, false>(reg, lds, j0, a.tw);
+      const float ct = static_cast<float>(c.ct);
+      const float ca = static_cast<float>(c.ca);
+#pragma unroll
+      for (int t = 0; t < EN; ++t) {
+        const float2 gv = reg[t];
+        const float2 v = ck[j0 + P * t];
+        // conj(g) v
+        const float re = gv.x * v.x + gv.y * v.y;
+        const float im = gv.x * v.y - gv.y * v.x;
+        acc[t] += -ct * im - ca * re;
+        if constexpr (MODE == ROW_ADJ_MID) reg[t] = cmul(conjf2(transmission(hreg[t], c)), gv);
+      }
+      if constexpr (MODE == ROW_ADJ_MID) {
+        fft<M, false, HALF>(reg, lds, j0, a.tw);
+        if (active) {
+#pragma unroll
+          for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
+        }
+      }
+    }
+    if (active) {
+      float* dst = a.dh_part +
+                   (static_cast<size_t>(a.chunk_base + blockIdx.y) * a.layers + a.layer) * nn +
+                   static_cast<size_t>(y) * N;
+      if (a.accumulate) {
+#pragma unroll
+        for (int t = 0; t < EN; ++t) dst[j0 + P * t] += acc[t];
+      } else {
+#pragma unroll
+        for (int t = 0; t < EN; ++t) dst[j0 + P * t] = acc[t];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Column pass.  A block owns TX adjacent columns of one wavelength's plane: it stages the
+// [rows][TX] tile through LDS (coalesced 8*TX-byte row segments), each transform group
+// then runs forward FFT -> transfer function -> inverse FFT on its column in registers, and
+// the kept rows go back through the same LDS tile.
+// ------------------------------------------------------------------------------------------
+template <int M, int PAD, bool CONJ, int TX>
+__global__ void __launch_bounds__(TX * Geo<M>::P) col_kernel(ColArgs a) {
+  constexpr int E = Geo<M>::E;
+  constexpr int P = Geo<M>::P;
+  constexpr int NT = TX * P;
+  constexpr int LD = M + 1;
+  constexpr int EN = E / PAD;
+  constexpr bool HALF = (PAD == 2);
+  __shared__ float2 tile[TX * LD];
+
+  const int N = M / PAD;
+  const int kx0 = blockIdx.x * TX;
+  float2* spec = a.spec + static_cast<size_t>(blockIdx.y) * N * M;
+  const WlConst c = a.wl[a.w_begin + blockIdx.y];
+
+  const int cc = threadIdx.x % TX;
+  const int yy = threadIdx.x / TX;
+  for (int y = a.in_lo + yy; y < a.in_hi; y += NT / TX)
+    tile[cc * LD + y] = spec[static_cast<size_t>(y) * M + kx0 + cc];
+  __syncthreads();
+
+  const int g = threadIdx.x / P;
+  const int j0 = threadIdx.x % P;
+  float2* lds = tile + g * LD;
+  float2 reg[E];
+#pragma unroll
+  for (int t = 0; t < EN; ++t) {
+    const int y = j0 + P * t;
+    reg[t] = (y >= a.in_lo && y < a.in_hi) ? lds[y] : make_float2(0.f, 0.f);
+  }
+  wave_sync();
+  fft<M, false, HALF>(reg, lds, j0, a.tw);
+
+  // transfer function: H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0
+  const int kx = kx0 + g;
+  const int kxs = kx < M / 2 ? kx : kx - M;
+  const double base = c.q0 - static_cast<double>(kxs * kxs);
+  const float inv_m2 = 1.0f / (static_cast<float>(M) * static_cast<float>(M));
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int ky = j0 + P * t;
+    const int kys = ky < M / 2 ? ky : ky - M;
+    const double q = base - static_cast<double>(kys * kys);
+    if (q > 0.0) {
+      float2 hh = cis_rev(a.zrev * sqrt(q));
+      if constexpr (CONJ) hh.y = -hh.y;
+      reg[t] = cscale(cmul(reg[t], hh), inv_m2);
+    } else {
+      reg[t] = make_float2(0.f, 0.f);
+    }
+  }
+  fft<M, true, false>(reg, lds, j0, a.tw);
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < EN; ++t) {
+    const int y = j0 + P * t;
+    if (y >= a.out_lo && y < a.out_hi) lds[y] = reg[t];
+  }
+  __syncthreads();
+  for (int y = a.out_lo + yy; y < a.out_hi; y += NT / TX)
+    spec[static_cast<size_t>(y) * M + kx0 + cc] = tile[cc * LD + y];
+}
+
+// ------------------------------------------------------------------------------------------
+// Small kernels
+// ------------------------------------------------------------------------------------------
+__global__ void bin_intensity_kernel(const float2* __restrict__ ofov, float* __restrict__ out,
+                                     int w_count, int fov, int bin) {
+  const int T = fov / bin;
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t total = static_cast<size_t>(w_count) * T * T;
+  if (i >= total) return;
+  const int w = static_cast<int>(i / (static_cast<size_t>(T) * T));
+  const int r = static_cast<int>(i % (static_cast<size_t>(T) * T));
+  const int ty = r / T, tx = r % T;
+  const float2* o = ofov + static_cast<size_t>(w) * fov * fov;
+  float s = 0.f;
+  for (int a = 0; a < bin; ++a)
+    for (int b = 0; b < bin; ++b) {
+      const float2 v = o[static_cast<size_t>(ty * bin + a) * fov + tx * bin + b];
+      s += v.x * v.x + v.y * v.y;
+    }
+  out[i] = s;
+}
+
+constexpr int kLossThreads = 256;
+
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kLossThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// One block per wavelength: sums in double in a fixed tree order (bitwise reproducible).
+__global__ void __launch_bounds__(kLossThreads)
+loss_kernel(const float* __restrict__ I, const float* __restrict__ tau, float* __restrict__ dl_di,
+            double* __restrict__ per_wl, int W, int T) {
+  __shared__ double sh[kLossThreads];
+  const int w = blockIdx.x;
+  const int P = T * T;
+  const float* Iw = I + static_cast<size_t>(w) * P;
+  const float* tw = tau + static_cast<size_t>(w) * P;
+  double si = 0.0, st = 0.0;
+  for (int p = threadIdx.x; p < P; p += kLossThreads) {
+    si += Iw[p];
+    st += tw[p];
+  }
+  const double S = block_sum(si, sh);
+  const double St = block_sum(st, sh);
+  const double rS = S > 0.0 ? 1.0 / S : 0.0;
+  const double rSt = St > 0.0 ? 1.0 / St : 0.0;
+  double sd2 = 0.0, sdi = 0.0;
+  for (int p = threadIdx.x; p < P; p += kLossThreads) {
+    const double ih = Iw[p] * rS;
+    const double d = ih - tw[p] * rSt;
+    sd2 += d * d;
+    sdi += d * ih;
+  }
+  const double D2 = block_sum(sd2, sh);
+  const double inner = block_sum(sdi, sh);
+  if (threadIdx.x == 0) per_wl[w] = D2 / P;
+  if (dl_di) {
+    const double k = 2.0 * rS / (static_cast<double>(W) * P);
+    float* gw = dl_di + static_cast<size_t>(w) * P;
+    for (int p = threadIdx.x; p < P; p += kLossThreads) {
+      const double ih = Iw[p] * rS;
+      const double d = ih - tw[p] * rSt;
+      gw[p] = static_cast<float>(k * (d - inner));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kLossThreads)
+loss_sum_kernel(const double* __restrict__ per_wl, double* __restrict__ loss, int W) {
+  __shared__ double sh[kLossThreads];
+  double s = 0.0;
+  for (int w = threadIdx.x; w < W; w += kLossThreads) s += per_wl[w];
+  const double tot = block_sum(s, sh);
+  if (threadIdx.x == 0) *loss = tot / W;
+}
+
+__global__ void dh_reduce_kernel(const float* __restrict__ part, float* __restrict__ dh, int nchunk,
+                                 int64_t per_chunk) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= per_chunk) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[c * per_chunk + i];
+  dh[i] = static_cast<float>(s);
+}
+
+__global__ void fill_zero_kernel(float* p, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+template <int M, int PAD>
+static hipError_t row_dispatch_mode(int mode, const RowArgs& a, dim3 grid, hipStream_t s) {
+  switch (mode) {
+    case ROW_FWD_FIRST: row_kernel<M, PAD, ROW_FWD_FIRST><<<grid, kRowThreads, 0, s>>>(a); break;
+    case ROW_FWD_MID: row_kernel<M, PAD, ROW_FWD_MID><<<grid, kRowThreads, 0, s>>>(a); break;
+    case ROW_FWD_LAST: row_kernel<M, PAD, ROW_FWD_LAST><<<grid, kRowThreads, 0, s>>>(a); break;
+    case ROW_ADJ_SEED: row_kernel<M, PAD, ROW_ADJ_SEED><<<grid, kRowThreads, 0, s>>>(a); break;
+    case ROW_ADJ_MID: row_kernel<M, PAD, ROW_ADJ_MID><<<grid, kRowThreads, 0, s>>>(a); break;
+    case ROW_ADJ_LAST: row_kernel<M, PAD, ROW_ADJ_LAST><<<grid, kRowThreads, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int M>
+static hipError_t row_dispatch_pad(int pad, int mode, const RowArgs& a, dim3 grid, hipStream_t s) {
+  if (pad == 2) return row_dispatch_mode<M, 2>(mode, a, grid, s);
+  if (pad == 1) return row_dispatch_mode<M, 1>(mode, a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+#define DPX_FOR_EACH_M(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
+
+bool fft_size_supported(int M) {
+  switch (M) {
+#define DPX_CASE(m) case m:
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+int row_lanes_per_transform(int M) {
+  switch (M) {
+#define DPX_CASE(m) case m: return Geo<m>::P;
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      return 0;
+  }
+}
+
+hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,
+                      hipStream_t s) {
+  dim3 grid(n_row_blocks, n_w_blocks);
+  switch (M) {
+#define DPX_CASE(m) case m: return row_dispatch_pad<m>(pad, mode, a, grid, s);
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int M, int PAD, int TX>
+static hipError_t col_dispatch_conj(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
+  dim3 grid(M / TX, w_count);
+  if (conj)
+    col_kernel<M, PAD, true, TX><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+  else
+    col_kernel<M, PAD, false, TX><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int M>
+static hipError_t col_dispatch(int pad, bool conj, int tx, const ColArgs& a, int w_count,
+                               hipStream_t s) {
+  // TX columns per block must make whole wavefronts
+  if (tx == 8 && 8 * Geo<M>::P >= 64) {
+    if (pad == 2) return col_dispatch_conj<M, 2, 8>(conj, a, w_count, s);
+    if (pad == 1) return col_dispatch_conj<M, 1, 8>(conj, a, w_count, s);
+  } else {
+    if (pad == 2) return col_dispatch_conj<M, 2, 16>(conj, a, w_count, s);
+    if (pad == 1) return col_dispatch_conj<M, 1, 16>(conj, a, w_count, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_col(int M, int pad, bool conj, int tx, const ColArgs& a, int w_count, hipStream_t s) {
+  switch (M) {
+#define DPX_CASE(m) case m: return col_dispatch<m>(pad, conj, tx, a, w_count, s);
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bin_intensity(const float2* ofov, float* out, int w_count, int fov, int bin,
+                                hipStream_t s) {
+  const int T = fov / bin;
+  const size_t total = static_cast<size_t>(w_count) * T * T;
+  const int th = 256;
+  bin_intensity_kernel<<<static_cast<unsigned>((total + th - 1) / th), th, 0, s>>>(ofov, out, w_count,
+                                                                                 fov, bin);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(const float* I, const float* tau, float* dl_di, double* per_wl, int W, int T,
+                       hipStream_t s) {
+  loss_kernel<<<W, kLossThreads, 0, s>>>(I, tau, dl_di, per_wl, W, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_sum(const double* per_wl, double* loss, int W, hipStream_t s) {
+  loss_sum_kernel<<<1, kLossThreads, 0, s>>>(per_wl, loss, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_dh_reduce(const float* part, float* dh, int nchunk, int64_t per_chunk,
+                            hipStream_t s) {
+  const int th = 256;
+  dh_reduce_kernel<<<static_cast<unsigned>((per_chunk + th - 1) / th), th, 0, s>>>(part, dh, nchunk,
+                                                                                 per_chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int th = 256;
+  fill_zero_kernel<<<static_cast<unsigned>((n + th - 1) / th), th, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+}  // namespace dpx

@@ -1,0 +1,306 @@
+// Register/LDS Stockham FFT for gfx950 wavefronts.
+//
+// A length-M transform is owned by a group of P = M / E lanes; every lane keeps E complex
+// values in registers in the strided layout  lane j0 holds element j0 + P*t, t = 0..E-1.
+// With this layout every Stockham radix-R stage (R divides E) finds all R inputs of its
+// butterflies in the lane's own registers; only the outputs of a non-final stage are
+// scattered, so they go through the group's LDS region and come back strided.  The final
+// stage writes its outputs exactly where its inputs were, so the transform ends in the same
+// strided natural order it started in, with (#stages - 1) LDS round trips.
+//
+// Forward transforms use exp(-2 pi i k n / M), inverse ones exp(+2 pi i k n / M), both
+// unnormalised.  Inter-stage twiddles come from a table tw[m] = exp(-2 pi i m / M) built on
+// the host in double precision from the exact integer index m; inverse stages conjugate it.
+// Twiddles inside a radix-R butterfly are compile-time constants.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace dpx {
+
+// ------------------------------------------------------------------------------------------
+// complex helpers (float2 = interleaved re, im)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward quarter turn) / +i
+__device__ __forceinline__ float2 mul_negi(float2 a) { return make_float2(a.y, -a.x); }
+__device__ __forceinline__ float2 mul_posi(float2 a) { return make_float2(-a.y, a.x); }
+
+// ------------------------------------------------------------------------------------------
+// compile-time helpers
+// ------------------------------------------------------------------------------------------
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// sin / cos of 2 pi num / den by a Taylor series on the angle reduced to (-pi, pi]
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 40; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 40; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double reduced_angle(int num, int den) {
+  int m = ((num % den) + den) % den;
+  if (2 * m > den) m -= den;
+  return 2.0 * kPi * static_cast<double>(m) / static_cast<double>(den);
+}
+constexpr double cos2pi(int num, int den) { return taylor_cos(reduced_angle(num, den)); }
+constexpr double sin2pi(int num, int den) { return taylor_sin(reduced_angle(num, den)); }
+
+// first factor A of a composite radix R = A * B (even whenever R is, so zero pruning passes on)
+constexpr int first_factor(int r) {
+  if (r == 8) return 2;
+  if (r % 4 == 0) return 4;
+  if (r % 2 == 0) return 2;
+  if (r % 3 == 0) return 3;
+  return r;
+}
+
+// v * W_R^e with W_R = exp(-2 pi i / R) (forward) or exp(+2 pi i / R) (inverse); e known at
+// compile time, multiples of pi/4 are special-cased.
+template <int R, int E, bool INV>
+__device__ __forceinline__ float2 twc(float2 v) {
+  constexpr int e = ((E % R) + R) % R;
+  if constexpr (e == 0) {
+    return v;
+  } else if constexpr ((8 * e) % R == 0) {
+    constexpr int oct = (8 * e) / R;  // angle = oct * pi / 4 (clockwise for forward)
+    constexpr float h = 0.70710678118654752440f;
+    // forward: multiply by exp(-i oct pi/4); inverse: exp(+i oct pi/4)
+    constexpr int o = INV ? (8 - oct) % 8 : oct;
+    if constexpr (o == 2) return mul_negi(v);
+    else if constexpr (o == 4) return make_float2(-v.x, -v.y);
+    else if constexpr (o == 6) return mul_posi(v);
+    else if constexpr (o == 1) return make_float2((v.x + v.y) * h, (v.y - v.x) * h);
+    else if constexpr (o == 3) return make_float2((v.y - v.x) * h, -(v.x + v.y) * h);
+    else if constexpr (o == 5) return make_float2(-(v.x + v.y) * h, (v.x - v.y) * h);
+    else return make_float2((v.x - v.y) * h, (v.x + v.y) * h);  // o == 7
+  } else {
+    constexpr float c = static_cast<float>(cos2pi(e, R));
+    constexpr float s = static_cast<float>(INV ? sin2pi(e, R) : -sin2pi(e, R));
+    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// radix-R DFT on R registers, natural order in and out.  HALF: inputs R/2..R-1 are zero and
+// are not read (zero-padded first stage).
+// ------------------------------------------------------------------------------------------
+template <int R, bool INV, bool HALF>
+struct DFT;
+
+template <bool INV, bool HALF>
+struct DFT<2, INV, HALF> {
+  static __device__ __forceinline__ void run(float2* v) {
+    if constexpr (HALF) {
+      v[1] = v[0];
+    } else {
+      float2 a = v[0], b = v[1];
+      v[0] = cadd(a, b);
+      v[1] = csub(a, b);
+    }
+  }
+};
+
+template <bool INV, bool HALF>
+struct DFT<3, INV, HALF> {
+  static_assert(!HALF, "radix-3 stages are never zero-pruned");
+  static __device__ __forceinline__ void run(float2* v) {
+    constexpr float c = -0.5f;
+    constexpr float s = INV ? 0.86602540378443864676f : -0.86602540378443864676f;
+    float2 a = v[0], b = v[1], d = v[2];
+    float2 sum = cadd(b, d), dif = csub(b, d);
+    float2 m = make_float2(a.x + c * sum.x, a.y + c * sum.y);
+    // i s (b - d)
+    float2 r = make_float2(-s * dif.y, s * dif.x);
+    v[0] = cadd(a, sum);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+
+template <bool INV, bool HALF>
+struct DFT<4, INV, HALF> {
+  static __device__ __forceinline__ void run(float2* v) {
+    if constexpr (HALF) {
+      float2 a = v[0], b = v[1];
+      float2 ib = INV ? mul_posi(b) : mul_negi(b);
+      v[0] = cadd(a, b);
+      v[2] = csub(a, b);
+      v[1] = cadd(a, ib);
+      v[3] = csub(a, ib);
+    } else {
+      float2 a = v[0], b = v[1], c = v[2], d = v[3];
+      float2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = csub(b, d);
+      float2 id1 = INV ? mul_posi(d1) : mul_negi(d1);
+      v[0] = cadd(s0, s1);
+      v[2] = csub(s0, s1);
+      v[1] = cadd(d0, id1);
+      v[3] = csub(d0, id1);
+    }
+  }
+};
+
+// Composite R = A * B:  n = B n1 + n2,  k = k1 + A k2.
+//   Y[n2][k1] = DFT_A over n1 of x[B n1 + n2];  Y *= W_R^(n2 k1);  X[k1 + A k2] = DFT_B over n2.
+// Zero inputs x[n >= R/2] are exactly the n1 >= A/2 terms, so HALF passes to the A-point DFTs.
+template <int R, bool INV, bool HALF>
+struct DFT {
+  static constexpr int A = first_factor(R);
+  static constexpr int B = R / A;
+  static_assert(A > 1 && A < R, "unsupported radix");
+  static_assert(!HALF || A % 2 == 0, "zero pruning needs an even first factor");
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 y[R];
+    static_for<0, B>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      float2 t[A];
+      static_for<0, A>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        if constexpr (!HALF || n1 < A / 2) t[n1] = v[B * n1 + n2];
+      });
+      DFT<A, INV, HALF>::run(t);
+      static_for<0, A>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        y[n2 * A + k1] = twc<R, n2 * k1, INV>(t[k1]);
+      });
+    });
+    static_for<0, A>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      float2 t[B];
+      static_for<0, B>([&](auto n2c) {
+        constexpr int n2 = decltype(n2c)::value;
+        t[n2] = y[n2 * A + k1];
+      });
+      DFT<B, INV, false>::run(t);
+      static_for<0, B>([&](auto k2c) {
+        constexpr int k2 = decltype(k2c)::value;
+        v[k1 + A * k2] = t[k2];
+      });
+    });
+  }
+};
+
+// ------------------------------------------------------------------------------------------
+// radix plans: E registers per lane, radices of each stage (all divide E)
+// ------------------------------------------------------------------------------------------
+template <int M>
+struct Plan;
+template <> struct Plan<64>   { static constexpr int E = 16, NST = 2; static constexpr int R[4] = {16, 4, 0, 0}; };
+template <> struct Plan<96>   { static constexpr int E = 24, NST = 3; static constexpr int R[4] = {3, 8, 4, 0}; };
+template <> struct Plan<128>  { static constexpr int E = 16, NST = 2; static constexpr int R[4] = {16, 8, 0, 0}; };
+template <> struct Plan<192>  { static constexpr int E = 24, NST = 3; static constexpr int R[4] = {3, 8, 8, 0}; };
+template <> struct Plan<256>  { static constexpr int E = 16, NST = 2; static constexpr int R[4] = {16, 16, 0, 0}; };
+template <> struct Plan<384>  { static constexpr int E = 24, NST = 3; static constexpr int R[4] = {6, 8, 8, 0}; };
+template <> struct Plan<512>  { static constexpr int E = 16, NST = 3; static constexpr int R[4] = {8, 8, 8, 0}; };
+template <> struct Plan<1024> { static constexpr int E = 16, NST = 3; static constexpr int R[4] = {16, 16, 4, 0}; };
+
+template <int M>
+struct Geo {
+  static constexpr int E = Plan<M>::E;
+  static constexpr int P = M / E;  // lanes per transform
+  static_assert(P <= 64, "one transform must fit in a wavefront");
+  static_assert(64 % P == 0, "transforms must tile a wavefront");
+};
+
+// LDS ordering between the lanes of one transform.  A transform never spans more than one
+// wavefront, and a wavefront's LDS instructions execute in program order, so a wave-level
+// fence + barrier orders the scattered writes before the strided reads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One Stockham stage: radix R, NS = product of the radices of the earlier stages.
+template <int M, int R, int NS, bool LAST, bool INV, bool HALF>
+__device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds,
+                                               int j0, const float2* __restrict__ tw) {
+  constexpr int E = Geo<M>::E;
+  constexpr int P = Geo<M>::P;
+  constexpr int S = E / R;
+  static_assert(E % R == 0, "radix must divide the registers per lane");
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int j = j0 + P * s;
+    const int k = (NS > 1) ? (j % NS) : 0;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = reg[s + r * S];
+    if constexpr (NS > 1) {
+      constexpr int STRIDE = M / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * k * STRIDE];
+        if constexpr (INV) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    DFT<R, INV, HALF>::run(v);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) reg[s + r * S] = v[r];
+    } else {
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[base + r * NS] = v[r];
+    }
+  }
+  if constexpr (!LAST) {
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < E; ++t) reg[t] = lds[j0 + P * t];
+    wave_sync();
+  }
+}
+
+template <int M, int ST, int NS, bool INV, bool HALF>
+__device__ __forceinline__ void fft_stages(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
+                                           const float2* __restrict__ tw) {
+  if constexpr (ST < Plan<M>::NST) {
+    constexpr int R = Plan<M>::R[ST];
+    constexpr bool LAST = (ST + 1 == Plan<M>::NST);
+    stockham_stage<M, R, NS, LAST, INV, HALF && ST == 0>(reg, lds, j0, tw);
+    fft_stages<M, ST + 1, NS * R, INV, false>(reg, lds, j0, tw);
+  }
+}
+
+// Full length-M transform of the group's registers.  HALF: elements M/2..M-1 are zero
+// (zero-padded input); only used when the first radix is even.
+template <int M, bool INV, bool HALF>
+__device__ __forceinline__ void fft(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
+                                    const float2* __restrict__ tw) {
+  constexpr bool H = HALF && (Plan<M>::R[0] % 2 == 0);
+  if constexpr (HALF && !H) {
+#pragma unroll
+    for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);
+  }
+  fft_stages<M, 0, 1, INV, H>(reg, lds, j0, tw);
+}
+
+}  // namespace dpx

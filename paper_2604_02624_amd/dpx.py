@@ -1,0 +1,308 @@
+"""Python binding of the dpx C ABI (include/dpx.h): argument marshalling only.
+
+Every step of the propagation, loss and adjoint runs in the HIP library libdpx.so; torch
+supplies device memory (tensors) and the current HIP stream.  There is no fallback: if the
+library is missing or the GPU is absent, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdpx.so")
+
+DPX_OK, DPX_E_ARG, DPX_E_UNSUPPORTED, DPX_E_NOMEM, DPX_E_DEVICE, DPX_E_STATE = range(6)
+STATUS_NAMES = {0: "DPX_OK", 1: "DPX_E_ARG", 2: "DPX_E_UNSUPPORTED", 3: "DPX_E_NOMEM",
+                4: "DPX_E_DEVICE", 5: "DPX_E_STATE"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class CDesign(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("layers", ctypes.c_int32), ("n_wl", ctypes.c_int32),
+                ("fov", ctypes.c_int32), ("bin", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("n_medium", ctypes.c_double),
+                ("wl", _dp), ("n_mat", _dp), ("kappa", _dp), ("z", _dp)]
+
+
+class COpts(ctypes.Structure):
+    _fields_ = [("checkpoint_mode", ctypes.c_int32), ("wl_chunk", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("force_variant", ctypes.c_int32), ("check_finite", ctypes.c_int32),
+                ("max_workspace_bytes", ctypes.c_int64)]
+
+
+class CLayout(ctypes.Structure):
+    _fields_ = [("h_offset", ctypes.c_int64), ("h_count", ctypes.c_int64),
+                ("u_offset", ctypes.c_int64), ("u_count", ctypes.c_int64),
+                ("img_offset", ctypes.c_int64), ("img_count", ctypes.c_int64),
+                ("transform_len", ctypes.c_int32), ("target_side", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+class DpxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdpx.so (built by paper_2604_02624_amd.build).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2604_02624_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.dpx_opts_default.argtypes = [ctypes.POINTER(COpts)]
+    lib.dpx_opts_default.restype = None
+    lib.dpx_plan_create.argtypes = [ctypes.POINTER(CDesign), i32, ctypes.POINTER(COpts),
+                                    ctypes.POINTER(vp)]
+    lib.dpx_plan_query.argtypes = [ctypes.POINTER(CDesign), i32, ctypes.POINTER(COpts),
+                                   ctypes.POINTER(i64)]
+    lib.dpx_plan_destroy.argtypes = [vp]
+    lib.dpx_plan_layout.argtypes = [vp, i32, ctypes.POINTER(CLayout)]
+    lib.dpx_plan_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.dpx_forward.argtypes = [vp, vp, vp, vp, vp]
+    lib.dpx_loss.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.dpx_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    for f in ("dpx_plan_create", "dpx_plan_query", "dpx_plan_destroy", "dpx_plan_layout",
+              "dpx_plan_sizes", "dpx_forward", "dpx_loss", "dpx_backward"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.dpx_timing_enable.argtypes = [vp, i32]
+    lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+    lib.dpx_timing_enable.restype = ctypes.c_int
+    lib.dpx_timing_read.restype = ctypes.c_int
+    lib.dpx_last_error.argtypes = []
+    lib.dpx_last_error.restype = ctypes.c_char_p
+    lib.dpx_version.argtypes = []
+    lib.dpx_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(lib, status):
+    if status != DPX_OK:
+        raise DpxError(status, lib.dpx_last_error().decode())
+
+
+def _c_designs(designs):
+    """Build the ctypes design array; returns it with the numpy arrays it points into."""
+    keep = []
+    arr = (CDesign * len(designs))()
+    for i, d in enumerate(designs):
+        def vec(x):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(x, dtype=np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(_dp)
+        arr[i].n, arr[i].layers, arr[i].n_wl = d["n"], d["layers"], d["n_wl"]
+        arr[i].fov, arr[i].bin, arr[i].pad = d["fov"], d["bin"], d["pad"]
+        arr[i].dx, arr[i].n_medium = d["dx"], d["n_medium"]
+        arr[i].wl = vec(d["wl"])
+        arr[i].n_mat = vec(d["n_mat"])
+        arr[i].kappa = vec(d.get("kappa"))
+        arr[i].z = vec(d["z"])
+    return arr, keep
+
+
+def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0):
+    o = COpts()
+    lib.dpx_opts_default(ctypes.byref(o))
+    o.checkpoint_mode = checkpoint_mode
+    o.wl_chunk = wl_chunk
+    o.force_variant = force_variant
+    o.max_workspace_bytes = max_workspace_bytes
+    return o
+
+
+def plan_query(designs, **opts) -> int:
+    """Device bytes a plan would allocate (host-only validation, no GPU needed)."""
+    lib = load_library()
+    arr, _keep = _c_designs(designs)
+    o = _opts(lib, **opts)
+    out = ctypes.c_int64(0)
+    _check(lib, lib.dpx_plan_query(arr, len(designs), ctypes.byref(o), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A dpx plan over one or more independent designs (dicts as produced by
+    ``paper_2604_02624_amd.workloads``).  Device buffers are torch tensors on the current
+    device, packed over designs as the C ABI describes."""
+
+    def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
+                 force_variant: int = -1, max_workspace_bytes: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.designs = list(designs)
+        arr, _keep = _c_designs(self.designs)
+        o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
+                                                  ctypes.byref(h)))
+        self._h = h
+        self.checkpoint_mode = checkpoint_mode
+        hc, uc, ic = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(self.lib, self.lib.dpx_plan_sizes(self._h, ctypes.byref(hc), ctypes.byref(uc),
+                                                 ctypes.byref(ic)))
+        self.h_count, self.u_count, self.img_count = hc.value, uc.value, ic.value
+        self.layouts = [self.layout(i) for i in range(len(self.designs))]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.dpx_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def layout(self, i: int) -> dict:
+        lo = CLayout()
+        _check(self.lib, self.lib.dpx_plan_layout(self._h, i, ctypes.byref(lo)))
+        return {f: getattr(lo, f) for f, _ in CLayout._fields_}
+
+    # -------------------------------------------------------------- packing helpers
+    def pack_heights(self, hs, device="cuda"):
+        import torch
+        return torch.cat([torch.as_tensor(np.ascontiguousarray(h, np.float32)).reshape(-1)
+                          for h in hs]).to(device)
+
+    def pack_images(self, imgs, device="cuda"):
+        import torch
+        return torch.cat([torch.as_tensor(np.ascontiguousarray(t, np.float32)).reshape(-1)
+                          for t in imgs]).to(device)
+
+    def unpack_images(self, flat):
+        out = []
+        for d, lo in zip(self.designs, self.layouts):
+            T = lo["target_side"]
+            out.append(flat[lo["img_offset"]:lo["img_offset"] + lo["img_count"]].reshape(d["n_wl"], T, T))
+        return out
+
+    def unpack_heights(self, flat):
+        out = []
+        for d, lo in zip(self.designs, self.layouts):
+            out.append(flat[lo["h_offset"]:lo["h_offset"] + lo["h_count"]].reshape(d["layers"], d["n"], d["n"]))
+        return out
+
+    # -------------------------------------------------------------- calls
+    def forward(self, h, u_in=None, out=None, stream=None):
+        import torch
+        self._check_dev(h, self.h_count, torch.float32, "h")
+        if u_in is not None:
+            self._check_dev(u_in, 2 * self.u_count, torch.float32, "u_in")
+        if out is None:
+            out = torch.empty(self.img_count, dtype=torch.float32, device=h.device)
+        self._check_dev(out, self.img_count, torch.float32, "intensity")
+        _check(self.lib, self.lib.dpx_forward(self._h, _ptr(h), _ptr(u_in), _ptr(out), _stream(stream)))
+        return out
+
+    def loss(self, intensity, target, loss_out=None, dl_di=None, want_grad=True, stream=None):
+        import torch
+        self._check_dev(intensity, self.img_count, torch.float32, "intensity")
+        self._check_dev(target, self.img_count, torch.float32, "target")
+        if loss_out is None:
+            loss_out = torch.empty(len(self.designs), dtype=torch.float64, device=intensity.device)
+        if want_grad and dl_di is None:
+            dl_di = torch.empty(self.img_count, dtype=torch.float32, device=intensity.device)
+        _check(self.lib, self.lib.dpx_loss(self._h, _ptr(intensity), _ptr(target), _ptr(loss_out),
+                                           _ptr(dl_di), _stream(stream)))
+        return loss_out, dl_di
+
+    def backward(self, h, u_in, dl_di, out=None, stream=None):
+        import torch
+        self._check_dev(h, self.h_count, torch.float32, "h")
+        self._check_dev(dl_di, self.img_count, torch.float32, "dl_di")
+        if out is None:
+            out = torch.empty(self.h_count, dtype=torch.float32, device=h.device)
+        self._check_dev(out, self.h_count, torch.float32, "dl_dh")
+        _check(self.lib, self.lib.dpx_backward(self._h, _ptr(h), _ptr(u_in), _ptr(dl_di), _ptr(out),
+                                               _stream(stream)))
+        return out
+
+    # -------------------------------------------------------------- per-pass timers
+    PASS_NAMES = ["col_fwd", "col_adj", "row_fwd_first", "row_fwd_mid", "row_fwd_last",
+                  "row_adj_seed", "row_adj_mid", "row_adj_last"]
+
+    def timing(self, enable: bool = True):
+        _check(self.lib, self.lib.dpx_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_read(self) -> dict:
+        out = {}
+        for i, name in enumerate(self.PASS_NAMES):
+            ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+            _check(self.lib, self.lib.dpx_timing_read(self._h, i, ctypes.byref(ms), ctypes.byref(n),
+                                                      ctypes.byref(b)))
+            out[name] = dict(ms=ms.value, launches=n.value, bytes=b.value)
+        return out
+
+    @staticmethod
+    def _check_dev(t, numel, dtype, name):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != numel:
+            raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def _autograd_function():
+    import torch
+
+    class DpxFunction(torch.autograd.Function):
+        """I = dpx_forward(h); the backward calls dpx_backward with dL/dI = grad_output."""
+
+        @staticmethod
+        def forward(ctx, h, plan, u_in=None):
+            I = plan.forward(h, u_in)
+            ctx.plan = plan
+            ctx.save_for_backward(h)
+            ctx.u_in = u_in
+            return I
+
+        @staticmethod
+        def backward(ctx, g):
+            (h,) = ctx.saved_tensors
+            dh = ctx.plan.backward(h, ctx.u_in, g.contiguous())
+            return dh, None, None
+
+    return DpxFunction
+
+
+_DpxFunction = None
+
+
+def dpx_intensity(h, plan: Plan, u_in=None):
+    """Differentiable intensity images (packed) as a function of the packed heights."""
+    global _DpxFunction
+    if _DpxFunction is None:
+        _DpxFunction = _autograd_function()
+    return _DpxFunction.apply(h, plan, u_in)

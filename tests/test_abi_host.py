@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every function
+the header declares, and the host-only dry run validates designs and sizes workspaces."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_02624_amd import dpx, workloads as wk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpx.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(dpx_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dpx.LIB_PATH):
+        pytest.fail("libdpx.so is not built (run python -m paper_2604_02624_amd.build)")
+    return dpx.load_library()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for f in ("dpx_plan_create", "dpx_plan_destroy", "dpx_forward", "dpx_loss", "dpx_backward",
+              "dpx_last_error", "dpx_plan_query", "dpx_plan_layout"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(dpx.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), f"{name} declared in dpx.h but not exported"
+    assert b"gfx950" in lib.dpx_version()
+
+
+def _query(designs, **kw):
+    return dpx.plan_query(designs, **kw)
+
+
+def test_query_workspace_of_the_large_workload(lib):
+    d = wk.make_workload(1)["designs"][0]
+    b = _query([d])
+    N, M, K, W, F = 64, 128, 2, 6, 32
+    spec = W * N * M * 8
+    ck = K * W * N * N * 8
+    assert b >= spec + ck + W * F * F * 8
+
+
+def test_query_store_vs_recompute_memory(lib):
+    d = wk.make_design(n=512, layers=4, wl=np.linspace(450e-9, 750e-9, 4096), n_mat=1.5, dx=3e-7,
+                       z=3e-5, fov=64)
+    store = _query([d])
+    rec = _query([d], checkpoint_mode=1, wl_chunk=64)
+    assert store > 48 * 2 ** 30            # 16 GiB spectra + 32 GiB checkpoints
+    assert rec < 2 * 2 ** 30
+    assert store < 288e9                    # fits one MI355X
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n", 63, dpx.DPX_E_ARG),
+    ("n", 0, dpx.DPX_E_ARG),
+    ("layers", 0, dpx.DPX_E_ARG),
+    ("fov", 65, dpx.DPX_E_ARG),
+    ("fov", 31, dpx.DPX_E_ARG),
+    ("bin", 3, dpx.DPX_E_ARG),
+    ("pad", 3, dpx.DPX_E_ARG),
+    ("dx", -1.0, dpx.DPX_E_ARG),
+    ("dx", float("nan"), dpx.DPX_E_ARG),
+    ("n", 80, dpx.DPX_E_UNSUPPORTED),
+])
+def test_query_rejects_bad_designs(lib, field, value, status):
+    d = dict(wk.make_workload(1)["designs"][0])
+    d[field] = value
+    with pytest.raises(dpx.DpxError) as e:
+        _query([d])
+    assert e.value.status == status
+    assert len(str(e.value)) > 12
+
+
+def test_query_rejects_bad_arrays(lib):
+    d = dict(wk.make_workload(1)["designs"][0])
+    d["wl"] = d["wl"].copy()
+    d["wl"][2] = 0.0
+    with pytest.raises(dpx.DpxError) as e:
+        _query([d])
+    assert e.value.status == dpx.DPX_E_ARG and "wl[2]" in str(e.value)
+    d = dict(wk.make_workload(1)["designs"][0])
+    d["z"] = np.array([1e-5, -1e-6])
+    with pytest.raises(dpx.DpxError):
+        _query([d])
+    d = dict(wk.make_workload(1)["designs"][0])
+    d["kappa"] = -np.ones(6)
+    with pytest.raises(dpx.DpxError):
+        _query([d])
+
+
+def test_query_rejects_bad_options(lib):
+    d = wk.make_workload(1)["designs"][0]
+    with pytest.raises(dpx.DpxError):
+        _query([d], checkpoint_mode=2)
+    with pytest.raises(dpx.DpxError):
+        _query([d], force_variant=5)
+
+
+def test_null_plan_and_pointers_are_errors(lib):
+    assert lib.dpx_forward(None, None, None, None, None) == dpx.DPX_E_ARG
+    assert b"plan" in lib.dpx_last_error()
+    assert lib.dpx_backward(None, None, None, None, None, None) == dpx.DPX_E_ARG
+    assert lib.dpx_loss(None, None, None, None, None, None) == dpx.DPX_E_ARG
+    assert lib.dpx_plan_destroy(None) == dpx.DPX_OK
+
+
+def test_every_workload_is_accepted(lib):
+    for cfg in (1, 3, 4, 5):
+        w = wk.make_workload(cfg)
+        assert _query(w["designs"]) > 0

@@ -1,0 +1,332 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, on the GPU.
+
+Intensities: per-wavelength relative L2 <= 1e-5 against the FP64 oracle.  Gradients: relative
+L2 <= 1e-3 against central finite differences of the FP64 oracle (64 pixels per layer plus
+8 random directions, step 1e-3 lambda_m) and against the oracle's own adjoint.  At the large
+sizes the GPU runs the whole workload in the launch configuration the benchmark uses and the
+oracle recomputes sampled wavelengths one by one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dpx_oracle as o
+from paper_2604_02624_amd import workloads as wk
+
+pytestmark = pytest.mark.gpu
+
+INT_TOL = 1e-5
+GRAD_TOL = 1e-3
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2604_02624_amd import dpx
+    dpx.load_library()
+    return torch
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def per_wl_rel(a, b):
+    return np.array([rel_l2(a[i], b[i]) for i in range(a.shape[0])])
+
+
+def run_gpu(torch, designs, hs, taus, u_ins=None, backward=True, dl_di=None, **plan_kw):
+    from paper_2604_02624_amd import dpx
+    plan = dpx.Plan(designs, **plan_kw)
+    h = plan.pack_heights(hs)
+    tau = plan.pack_images(taus)
+    u = None
+    if u_ins is not None:
+        u = torch.cat([torch.view_as_real(torch.as_tensor(np.asarray(x, np.complex64))).reshape(-1)
+                       for x in u_ins]).cuda()
+    I = plan.forward(h, u)
+    L, g = plan.loss(I, tau)
+    out = dict(plan=plan, h=h, u=u, I=I, L=L, g=g)
+    if backward:
+        gin = g if dl_di is None else plan.pack_images(dl_di)
+        out["dh"] = plan.backward(h, u, gin)
+    torch.cuda.synchronize()
+    return out
+
+
+# ------------------------------------------------------------------------------------------
+# small workloads: full comparison
+# ------------------------------------------------------------------------------------------
+
+def test_forward_small_experiment_geometry(torch_dev):
+    say("forward, 2 layers 64x64 pad 128, 6 wavelengths")
+    w = wk.make_workload(1)
+    d, h = w["designs"][0], w["h"][0]
+    r = run_gpu(torch_dev, [d], [h], w["targets"], backward=False)
+    I_gpu = r["I"].cpu().numpy().reshape(6, 32, 32)
+    I_ref = o.forward(d, h, None, "naive")
+    errs = per_wl_rel(I_gpu, I_ref)
+    say(f"per-wavelength rel L2 {errs}")
+    assert errs.max() <= INT_TOL
+
+
+def test_forward_adjoint_small_vs_finite_differences(torch_dev):
+    say("forward + adjoint, 2 layers 64x64, 6 wavelengths, FD check")
+    w = wk.make_workload(2)
+    d, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
+    r = run_gpu(torch_dev, [d], [h], [tau])
+    I_gpu = r["I"].cpu().numpy().reshape(6, 32, 32)
+    I_ref = o.forward(d, h, None, "fft")
+    assert per_wl_rel(I_gpu, I_ref).max() <= INT_TOL
+    L_ref, g_ref, _ = o.loss(I_ref, tau)
+    assert abs(float(r["L"].cpu()[0]) - L_ref) <= 1e-4 * abs(L_ref)
+    assert rel_l2(r["g"].cpu().numpy().reshape(g_ref.shape), g_ref) <= 1e-4
+    dh_gpu = r["dh"].cpu().numpy().reshape(h.shape)
+    dh_ref = o.grad(d, h, None, g_ref, "fft")
+    say(f"gradient vs oracle adjoint {rel_l2(dh_gpu, dh_ref):.3e}")
+    assert rel_l2(dh_gpu, dh_ref) <= 1e-4
+    # central finite differences of the FP64 oracle: 64 pixels per layer + 8 directions
+    lam_m = 620e-9
+    delta = 1e-3 * lam_m
+    g = wk.rng(2, wk.STREAM_FD_PIXELS)
+    pix = [(l, int(g.integers(64)), int(g.integers(64))) for l in range(2) for _ in range(64)]
+    fd = o.fd_pixels(d, h, None, tau, pix, delta, "fft")
+    an = np.array([dh_gpu[p] for p in pix])
+    say(f"gradient vs FD (128 pixels) {rel_l2(an, fd):.3e}")
+    assert rel_l2(an, fd) <= GRAD_TOL
+    gd = wk.rng(2, wk.STREAM_FD_DIRS)
+    for _ in range(8):
+        v = gd.standard_normal(h.shape)
+        fdv = o.fd_direction(d, h, None, tau, v, delta / np.sqrt(v.size), "fft")
+        assert abs((dh_gpu * v).sum() - fdv) <= GRAD_TOL * abs(fdv)
+
+
+def test_input_field_absorption_and_binning(torch_dev):
+    say("u_in + kappa + bin 2, 3 layers 32x32 pad 64, 5 wavelengths")
+    g = np.random.default_rng(21)
+    wl = np.linspace(480e-9, 700e-9, 5)
+    d = wk.make_design(n=32, layers=3, wl=wl, n_mat=wk.cauchy_index(wl), dx=240e-9,
+                       z=[5e-6, 7e-6, 9e-6], fov=16, bin_=2, pad=2, kappa=np.linspace(0, 0.03, 5))
+    h = (g.random((3, 32, 32)) * 1.2e-6).astype(np.float32)
+    u = (g.standard_normal((32, 32)) + 1j * g.standard_normal((32, 32))).astype(np.complex64)
+    tau = g.random((5, 8, 8)).astype(np.float32)
+    r = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u])
+    I_ref = o.forward(d, h, u, "naive")
+    assert per_wl_rel(r["I"].cpu().numpy().reshape(5, 8, 8), I_ref).max() <= INT_TOL
+    _, g_ref, _ = o.loss(I_ref, tau)
+    r2 = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u], dl_di=[g_ref.astype(np.float32)])
+    dh_ref = o.grad(d, h, u, g_ref.astype(np.float32), "naive")
+    err = rel_l2(r2["dh"].cpu().numpy().reshape(h.shape), dh_ref)
+    say(f"gradient rel {err:.3e}")
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("n", [64, 96, 128, 192, 256, 512])
+def test_periodic_window_every_transform_length(torch_dev, n):
+    say(f"pad 1 (periodic), N = M = {n}")
+    g = np.random.default_rng(n)
+    wl = np.array([450e-9, 600e-9, 750e-9])
+    d = wk.make_design(n=n, layers=2, wl=wl, n_mat=1.5, dx=300e-9, z=[6e-6, 4e-6], fov=n // 2,
+                       pad=1)
+    h = (g.random((2, n, n)) * 1.2e-6).astype(np.float32)
+    tau = g.random((3, n // 2, n // 2)).astype(np.float32)
+    r = run_gpu(torch_dev, [d], [h], [tau])
+    I_ref = o.forward(d, h, None, "fft")
+    assert per_wl_rel(r["I"].cpu().numpy().reshape(I_ref.shape), I_ref).max() <= INT_TOL
+    L_ref, g_ref, _ = o.loss(I_ref, tau)
+    dh_ref = o.grad(d, h, None, g_ref, "fft")
+    assert rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref) <= 1e-4
+
+
+@pytest.mark.parametrize("n", [32, 48, 64, 96, 128, 192, 256, 512])
+def test_zero_padded_every_transform_length(torch_dev, n):
+    say(f"pad 2, N = {n}, M = {2 * n}")
+    g = np.random.default_rng(100 + n)
+    wl = np.array([450e-9, 610e-9, 750e-9])
+    d = wk.make_design(n=n, layers=2, wl=wl, n_mat=wk.cauchy_index(wl), dx=300e-9,
+                       z=[30e-6, 30e-6], fov=n // 4 * 2, pad=2)
+    h = (g.random((2, n, n)) * 1.17e-6).astype(np.float32)
+    F = n // 4 * 2
+    tau = g.random((3, F, F)).astype(np.float32)
+    r = run_gpu(torch_dev, [d], [h], [tau])
+    I_ref = o.forward(d, h, None, "fft")
+    errs = per_wl_rel(r["I"].cpu().numpy().reshape(I_ref.shape), I_ref)
+    say(f"rel L2 {errs}")
+    assert errs.max() <= INT_TOL
+    _, g_ref, _ = o.loss(I_ref, tau)
+    dh_ref = o.grad(d, h, None, g_ref, "fft")
+    assert rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref) <= 1e-4
+
+
+def test_single_layer_single_wavelength_edge(torch_dev):
+    say("K = 1, W = 1, F = N")
+    g = np.random.default_rng(5)
+    d = wk.make_design(n=64, layers=1, wl=np.array([532e-9]), n_mat=1.46, dx=266e-9, z=20e-6,
+                       fov=64, pad=2)
+    h = (g.random((1, 64, 64)) * 1e-6).astype(np.float32)
+    tau = g.random((1, 64, 64)).astype(np.float32)
+    r = run_gpu(torch_dev, [d], [h], [tau])
+    I_ref = o.forward(d, h, None, "naive")
+    assert rel_l2(r["I"].cpu().numpy().reshape(I_ref.shape), I_ref) <= INT_TOL
+    _, g_ref, _ = o.loss(I_ref, tau)
+    assert rel_l2(r["dh"].cpu().numpy().reshape(h.shape), o.grad(d, h, None, g_ref, "naive")) <= 1e-4
+
+
+# ------------------------------------------------------------------------------------------
+# batched workloads
+# ------------------------------------------------------------------------------------------
+
+def test_batched_five_layers_256(torch_dev):
+    say("batched: 5 layers 256x256 pad 512, 256 wavelengths (oracle on 6 sampled wavelengths)")
+    w = wk.make_workload(3)
+    d, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
+    sample = [0, 37, 101, 128, 200, 255]
+    I_ref = o.forward(d, h, None, "fft", wavelengths=sample)
+    _, g_s, _ = o.loss(I_ref, tau[sample])
+    dl_di = np.zeros((256, 64, 64), np.float32)
+    dl_di[sample] = g_s
+    r = run_gpu(torch_dev, [d], [h], [tau], dl_di=[dl_di])
+    I_gpu = r["I"].cpu().numpy().reshape(256, 64, 64)
+    errs = per_wl_rel(I_gpu[sample], I_ref)
+    say(f"rel L2 {errs}")
+    assert errs.max() <= INT_TOL
+    dh_ref = o.grad(d, h, None, g_s.astype(np.float32), "fft", wavelengths=sample)
+    err = rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref)
+    say(f"gradient rel {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_large_full_size_sampled(torch_dev):
+    say("large: 4 layers 512x512 pad 1024, 4096 wavelengths (oracle on 3 sampled wavelengths)")
+    w = wk.make_workload(4)
+    d, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
+    sample = [0, 2047, 4095]
+    I_ref = o.forward(d, h, None, "fft", wavelengths=sample)
+    _, g_s, _ = o.loss(I_ref, tau[sample])
+    dl_di = np.zeros((4096, 64, 64), np.float32)
+    dl_di[sample] = g_s
+    r = run_gpu(torch_dev, [d], [h], [tau], dl_di=[dl_di])
+    I_gpu = r["I"].cpu().numpy().reshape(4096, 64, 64)
+    errs = per_wl_rel(I_gpu[sample], I_ref)
+    say(f"rel L2 {errs}")
+    assert errs.max() <= INT_TOL
+    assert np.isfinite(I_gpu).all()
+    dh_ref = o.grad(d, h, None, g_s.astype(np.float32), "fft", wavelengths=sample)
+    err = rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref)
+    say(f"gradient rel {err:.3e}")
+    assert err <= 1e-4
+    # property at full size: each layer's gradient sums to ~0 (global-phase invariance)
+    dh = r["dh"].cpu().numpy().reshape(h.shape).astype(np.float64)
+    assert (np.abs(dh.sum(axis=(1, 2))) <= 1e-3 * np.abs(dh).sum(axis=(1, 2))).all()
+
+
+def test_uneven_designs_in_one_plan(torch_dev):
+    say("uneven: 64 designs, N in {96,128,192,256}, 2-5 layers, 6-512 wavelengths")
+    w = wk.make_workload(5)
+    ds, hs, taus = w["designs"], w["h"], w["targets"]
+    r = run_gpu(torch_dev, ds, hs, taus, backward=True)
+    plan = r["plan"]
+    Is = plan.unpack_images(r["I"].cpu())
+    gs = plan.unpack_images(r["g"].cpu())
+    dhs = plan.unpack_heights(r["dh"].cpu())
+    Ls = r["L"].cpu().numpy()
+    worst = 0.0
+    for i in range(0, 64, 7):
+        d = ds[i]
+        sample = sorted({0, d["n_wl"] - 1})
+        I_ref = o.forward(d, hs[i], None, "fft", wavelengths=sample)
+        errs = per_wl_rel(Is[i].numpy()[sample], I_ref)
+        worst = max(worst, errs.max())
+    say(f"worst sampled rel L2 {worst:.3e}")
+    assert worst <= INT_TOL
+    # loss and gradient on two small designs in full
+    for i in [j for j in range(64) if ds[j]["n_wl"] <= 24][:2]:
+        d = ds[i]
+        I_ref = o.forward(d, hs[i], None, "fft")
+        L_ref, g_ref, _ = o.loss(I_ref, taus[i])
+        assert abs(Ls[i] - L_ref) <= 1e-4 * L_ref
+        assert rel_l2(gs[i].numpy(), g_ref) <= 1e-4
+        dh_ref = o.grad(d, hs[i], None, gs[i].numpy(), "fft")
+        assert rel_l2(dhs[i].numpy(), dh_ref) <= 1e-4
+
+
+# ------------------------------------------------------------------------------------------
+# reproducibility, invariance, variants, error paths
+# ------------------------------------------------------------------------------------------
+
+def test_bitwise_repeatable_and_batch_invariant(torch_dev):
+    say("determinism + batch invariance (batched workload)")
+    w = wk.make_workload(3)
+    d, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
+    r1 = run_gpu(torch_dev, [d], [h], [tau])
+    r2 = run_gpu(torch_dev, [d], [h], [tau])
+    assert torch_dev.equal(r1["I"], r2["I"])
+    assert torch_dev.equal(r1["dh"], r2["dh"])
+    sub = [5, 77]
+    ds = wk.subset_wavelengths(d, sub)
+    rs = run_gpu(torch_dev, [ds], [h], [tau[sub]], backward=False)
+    I_full = r1["I"].reshape(256, 64, 64)[sub]
+    assert torch_dev.equal(rs["I"].reshape(2, 64, 64), I_full)
+
+
+def test_recompute_mode_and_column_variants_agree(torch_dev):
+    say("store vs recompute mode, column tile 8 vs 16")
+    w = wk.make_workload(3)
+    d, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
+    base = run_gpu(torch_dev, [d], [h], [tau])
+    rec = run_gpu(torch_dev, [d], [h], [tau], checkpoint_mode=1, wl_chunk=48)
+    assert torch_dev.equal(rec["I"], base["I"])
+    assert rel_l2(rec["dh"].cpu().numpy(), base["dh"].cpu().numpy()) <= 1e-6
+    for tx in (8, 16):
+        v = run_gpu(torch_dev, [d], [h], [tau], force_variant=tx)
+        assert torch_dev.equal(v["I"], base["I"])
+        assert torch_dev.equal(v["dh"], base["dh"])
+
+
+def test_error_paths(torch_dev):
+    say("error paths")
+    from paper_2604_02624_amd import dpx
+    w = wk.make_workload(1)
+    plan = dpx.Plan(w["designs"])
+    h = plan.pack_heights(w["h"])
+    g = torch_dev.zeros(plan.img_count, device="cuda")
+    with pytest.raises(dpx.DpxError) as e:
+        plan.backward(h, None, g)
+    assert e.value.status == dpx.DPX_E_STATE
+    I = plan.forward(h)
+    with pytest.raises(dpx.DpxError) as e:
+        plan.backward(h.clone(), None, g)
+    assert e.value.status == dpx.DPX_E_STATE
+    plan.backward(h, None, g)
+    with pytest.raises(ValueError):
+        plan.forward(h[:-1].contiguous())
+    lib = plan.lib
+    assert lib.dpx_forward(plan._h, None, None, dpx._ptr(I), None) == dpx.DPX_E_ARG
+    with pytest.raises(dpx.DpxError) as e:
+        dpx.Plan(w["designs"], max_workspace_bytes=1024)
+    assert e.value.status == dpx.DPX_E_NOMEM
+    torch_dev.cuda.synchronize()
+
+
+def test_autograd_function(torch_dev):
+    say("torch.autograd.Function wrapper")
+    from paper_2604_02624_amd import dpx
+    w = wk.make_workload(2)
+    plan = dpx.Plan(w["designs"])
+    h = plan.pack_heights(w["h"]).requires_grad_(True)
+    tau = plan.pack_images(w["targets"])
+    I = dpx.dpx_intensity(h, plan)
+    _, g = plan.loss(I.detach(), tau)
+    I.backward(g)
+    ref = plan.backward(h.detach(), None, g)
+    assert torch_dev.equal(h.grad, ref)
