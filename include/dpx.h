@@ -93,8 +93,12 @@ typedef struct dpx_opts {
                                1: backward recomputes the forward chunk by chunk */
   int32_t wl_chunk;         /* wavelengths per recompute chunk (0 = automatic) */
   int32_t use_graph;        /* reserved: capture launch sequences in HIP graphs */
-  int32_t autotune;         /* reserved: time kernel variants at plan creation */
-  int32_t force_variant;    /* -1 automatic; otherwise a column-pass tile width (8 or 16) */
+  int32_t autotune;         /* nonzero: dpx_plan_create times every column-pass variant on
+                               each distinct transform length and keeps the fastest */
+  int32_t force_variant;    /* -1: automatic (autotuned if asked, else a built-in choice per
+                               transform length); otherwise a column-pass variant index
+                               (see dpx_variant_count / dpx_variant_name).  Every variant
+                               gives the same results bit for bit. */
   int32_t check_finite;     /* reserved */
   int64_t max_workspace_bytes; /* 0 = no limit; otherwise plan creation fails with
                                   DPX_E_NOMEM if the plan would need more */
@@ -189,6 +193,13 @@ dpx_status dpx_timing_read(dpx_plan* plan, int32_t pass, double* total_ms, int64
 /* Message for the last failed call on this thread ("" if none).  Valid until the next call
  * on this thread. */
 const char* dpx_last_error(void);
+
+/* Column-pass kernel variants: count, and a short name for index v ("" if out of range). */
+int32_t dpx_variant_count(void);
+const char* dpx_variant_name(int32_t v);
+
+/* The column-pass variant the plan uses for design `design`. */
+dpx_status dpx_plan_variant(const dpx_plan* plan, int32_t design, int32_t* variant);
 
 /* Library version string. */
 const char* dpx_version(void);

@@ -56,7 +56,7 @@ struct Design {
   int w_per_block;   // wavelengths per row-pass block
   int nslots;        // dL/dh partial slots = ceil(wl_chunk / w_per_block)
   int row_group;     // rows per row-pass block
-  int col_tx;        // columns per column-pass block
+  int col_variant;   // column-pass kernel variant
   // device memory
   WlConst* d_wl = nullptr;
   float2* spec = nullptr;
@@ -107,9 +107,8 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
       return fail(DPX_E_ARG, "checkpoint_mode must be 0 or 1");
     if (o->wl_chunk < 0) return fail(DPX_E_ARG, "wl_chunk must be >= 0");
     if (o->max_workspace_bytes < 0) return fail(DPX_E_ARG, "max_workspace_bytes must be >= 0");
-    if (o->force_variant != -1 && o->force_variant != 0 && o->force_variant != 8 &&
-        o->force_variant != 16)
-      return fail(DPX_E_ARG, "force_variant must be -1, 8 or 16");
+    if (o->force_variant < -1 || o->force_variant >= dpx::kColVariants)
+      return fail(DPX_E_ARG, "force_variant must be -1 or a variant index below %d", dpx::kColVariants);
   }
   for (int i = 0; i < nd; ++i) {
     const dpx_design& d = ds[i];
@@ -172,9 +171,7 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   d.wl_chunk = chunk;
   d.w_per_block = wpb;
   d.nslots = (chunk + wpb - 1) / wpb;
-  // 16-column tiles give 128-byte row segments; at M = 1024 their 1024-thread blocks cap the
-  // registers at 128 per lane, so 8-column tiles are the default there
-  d.col_tx = (o.force_variant == 8 || o.force_variant == 16) ? o.force_variant : (d.M >= 1024 ? 8 : 16);
+  d.col_variant = o.force_variant >= 0 ? o.force_variant : dpx::default_col_variant(d.M);
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
   const int ck_w = (o.checkpoint_mode == 1) ? chunk : d.W;
   const int of_w = (o.checkpoint_mode == 1) ? chunk : d.W;
@@ -326,7 +323,7 @@ dpx_status run_col(dpx_plan* p, const Design& d, int layer, bool conj, int w0, i
   TimedLaunch t{conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD, nullptr, nullptr,
                 static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo))};
   DPX_TRY(timer_begin(p, s, t));
-  hipError_t e = dpx::launch_col(d.M, d.pad, conj, d.col_tx, c, wc, s);
+  hipError_t e = dpx::launch_col(d.M, d.pad, conj, d.col_variant, c, wc, s);
   if (e != hipSuccess) return fail(DPX_E_DEVICE, "column pass launch failed: %s", hipGetErrorString(e));
   DPX_TRY(timer_end(p, s, t));
   return DPX_OK;
@@ -376,6 +373,47 @@ dpx_status adjoint_chunk(dpx_plan* p, const Design& d, const float* h, const flo
   return DPX_OK;
 }
 
+// Times every column-pass variant on the design's first wavelengths (forward column pass
+// of layer 0 on a zeroed spectrum buffer) and keeps the fastest.  All variants produce the
+// same bits, so the choice changes speed only.
+dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
+  const int key = d.M * 4 + d.pad;
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    d.col_variant = it->second;
+    return DPX_OK;
+  }
+  const int wc = std::min(std::min(d.W, d.wl_chunk), 64);
+  DPX_HIP(hipMemset(d.spec, 0, static_cast<size_t>(wc) * d.N * d.M * 8));
+  hipEvent_t e0, e1;
+  DPX_HIP(hipEventCreate(&e0));
+  DPX_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_v = dpx::default_col_variant(d.M);
+  const bool was_timing = p->timing;
+  p->timing = false;
+  for (int v = 0; v < dpx::kColVariants; ++v) {
+    d.col_variant = v;
+    DPX_TRY(run_col(p, d, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
+    DPX_HIP(hipEventRecord(e0, nullptr));
+    for (int r = 0; r < 3; ++r) DPX_TRY(run_col(p, d, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
+    DPX_HIP(hipEventRecord(e1, nullptr));
+    DPX_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    DPX_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  p->timing = was_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  d.col_variant = best_v;
+  cache[key] = best_v;
+  return DPX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -395,6 +433,20 @@ void dpx_opts_default(dpx_opts* o) {
 const char* dpx_last_error(void) { return g_last_error.c_str(); }
 
 const char* dpx_version(void) { return "dpx 0.1 (gfx950)"; }
+
+int32_t dpx_variant_count(void) { return dpx::kColVariants; }
+
+const char* dpx_variant_name(int32_t v) {
+  return (v >= 0 && v < dpx::kColVariants) ? dpx::kColVariantNames[v] : "";
+}
+
+dpx_status dpx_plan_variant(const dpx_plan* p, int32_t i, int32_t* variant) {
+  if (!p || !variant) return fail(DPX_E_ARG, "plan and variant must not be NULL");
+  if (i < 0 || i >= static_cast<int>(p->designs.size()))
+    return fail(DPX_E_ARG, "design index %d out of range", i);
+  *variant = p->designs[i].col_variant;
+  return ok();
+}
 
 dpx_status dpx_plan_query(const dpx_design* ds, int32_t nd, const dpx_opts* opts, int64_t* bytes) {
   dpx_opts o;
@@ -491,6 +543,11 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
       }
       p->bytes += static_cast<int64_t>(d.M) * 8;
     }
+  }
+  if (st == DPX_OK && o.autotune && o.force_variant < 0) {
+    std::map<int, int> cache;
+    for (auto& d : p->designs)
+      if ((st = autotune_design(p, d, cache)) != DPX_OK) break;
   }
   if (st != DPX_OK) {
     std::string msg = g_last_error;

@@ -61,7 +61,11 @@ struct ColArgs {
 // launchers (dpx_kernels.hip); each returns a hipError_t from the launch
 hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,
                       hipStream_t s);
-hipError_t launch_col(int M, int pad, bool conj, int tx, const ColArgs& a, int w_count, hipStream_t s);
+constexpr int kColVariants = 4;
+extern const char* const kColVariantNames[kColVariants];
+int default_col_variant(int M);
+hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
+                      hipStream_t s);
 hipError_t launch_bin_intensity(const float2* ofov, float* out, int w_count, int fov, int bin,
                                 hipStream_t s);
 hipError_t launch_loss(const float* I, const float* tau, float* dl_di, double* per_wl, int W, int T,

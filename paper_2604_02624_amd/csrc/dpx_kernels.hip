@@ -10,21 +10,14 @@
 // shifts, so cropping the same corner returns the same N x N field.
 #include "dpx_internal.hpp"
 #include "fft.hpp"
+#include "phase.hpp"
 
 namespace dpx {
-
-// exp(+i 2 pi rev), with rev reduced to [-1/2, 1/2] in double precision first
-__device__ __forceinline__ float2 cis_rev(double rev) {
-  const double f = rev - rint(rev);
-  float s, c;
-  sincospif(2.0f * static_cast<float>(f), &s, &c);
-  return make_float2(c, s);
-}
 
 // Eq. 1 with the +j reading: t = exp(-ca h) exp(+i 2 pi rt h); phase argument in double.
 __device__ __forceinline__ float2 transmission(float h, const WlConst& c) {
   const double hd = static_cast<double>(h);
-  float2 t = cis_rev(c.rt * hd);
+  float2 t = cis_turns(c.rt * hd);
   if (c.ca != 0.0) {
     const float a = expf(-static_cast<float>(c.ca * hd));
     t.x *= a;
@@ -46,12 +39,13 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
   constexpr int G = kRowThreads / P;
   constexpr int EN = E / PAD;  // registers that hold x < N
   constexpr bool HALF = (PAD == 2);
-  __shared__ float2 lds_all[G * M];
+  constexpr int RG = Geo<M>::ROW_REGION;
+  __shared__ float2 lds_all[G * RG];
 
   const int N = M / PAD;
   const int g = threadIdx.x / P;
   const int j0 = threadIdx.x % P;
-  float2* lds = lds_all + g * M;
+  float2* lds = lds_all + g * RG;
   const int y_raw = a.row_lo + blockIdx.x * G + g;
   const bool active = y_raw < a.row_hi;
   const int y = active ? y_raw : a.row_lo;
@@ -183,7 +177,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
         const float re = gv.x * v.x + gv.y * v.y;
         const float im = gv.x * v.y - gv.y * v.x;
         acc[t] += -ct * im - ca * re;
-        if constexpr (MODE == ROW_ADJ_MID) reg[t] = cmul(conjf2(transmission(hreg[t], c)), gv);
+        if constexpr (MODE == ROW_ADJ_MID) reg[t] = cmulc(gv, transmission(hreg[t], c));
       }
       if constexpr (MODE == ROW_ADJ_MID) {
         fft<M, false, HALF>(reg, lds, j0, a.tw);
@@ -208,18 +202,28 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
   }
 }
 
+// H(kx, ky) / M^2 with the conjugate for the adjoint; 0 outside the propagating disc
+template <int M, bool CONJ>
+__device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
+  const int kys = ky < M / 2 ? ky : ky - M;
+  const double q = base - static_cast<double>(kys * kys);
+  const float2 hh = cis_turns<M * M>(zrev * sqrt_pos(q > 0.0 ? q : 1.0));
+  return q > 0.0 ? (CONJ ? conjf2(hh) : hh) : make_float2(0.f, 0.f);
+}
+
 // ------------------------------------------------------------------------------------------
 // Column pass.  A block owns TX adjacent columns of one wavelength's plane: it stages the
 // [rows][TX] tile through LDS (coalesced 8*TX-byte row segments), each transform group
 // then runs forward FFT -> transfer function -> inverse FFT on its column in registers, and
 // the kept rows go back through the same LDS tile.
 // ------------------------------------------------------------------------------------------
-template <int M, int PAD, bool CONJ, int TX>
-__global__ void __launch_bounds__(TX * Geo<M>::P) col_kernel(ColArgs a) {
+template <int M, int PAD, bool CONJ, int TX, bool MIRROR>
+__global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_per_eu(4)))
+col_kernel(ColArgs a) {
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
   constexpr int NT = TX * P;
-  constexpr int LD = M + 1;
+  constexpr int LD = Geo<M>::COL_REGION;  // one column's staging rows / exchange region
   constexpr int EN = E / PAD;
   constexpr bool HALF = (PAD == 2);
   __shared__ float2 tile[TX * LD];
@@ -247,23 +251,33 @@ __global__ void __launch_bounds__(TX * Geo<M>::P) col_kernel(ColArgs a) {
   wave_sync();
   fft<M, false, HALF>(reg, lds, j0, a.tw);
 
-  // transfer function: H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0
+  // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0.
   const int kx = kx0 + g;
   const int kxs = kx < M / 2 ? kx : kx - M;
   const double base = c.q0 - static_cast<double>(kxs * kxs);
-  const float inv_m2 = 1.0f / (static_cast<float>(M) * static_cast<float>(M));
+  if constexpr (MIRROR) {
+    // H depends on ky^2 only: lane j0 holds ky = j0 + P t, and for t >= E/2 the row M - ky
+    // is register E-1-t of lane P - j0 (lane 0 mirrors onto its own register E - t), so
+    // each lane evaluates E/2 + 1 rows and fetches the others across lanes.
+    constexpr int EH = E / 2;
+    float2 own[EH + 1];
 #pragma unroll
-  for (int t = 0; t < E; ++t) {
-    const int ky = j0 + P * t;
-    const int kys = ky < M / 2 ? ky : ky - M;
-    const double q = base - static_cast<double>(kys * kys);
-    if (q > 0.0) {
-      float2 hh = cis_rev(a.zrev * sqrt(q));
-      if constexpr (CONJ) hh.y = -hh.y;
-      reg[t] = cscale(cmul(reg[t], hh), inv_m2);
-    } else {
-      reg[t] = make_float2(0.f, 0.f);
+    for (int t = 0; t <= EH; ++t) own[t] = transfer<M, CONJ>(a.zrev, base, j0 + P * t);
+#pragma unroll
+    for (int t = 0; t < EH; ++t) reg[t] = cmul(reg[t], own[t]);
+    const int lane = threadIdx.x & 63;
+    const int src = ((lane - j0) + ((P - j0) & (P - 1))) << 2;
+#pragma unroll
+    for (int t = EH; t < E; ++t) {
+      float2 m;
+      m.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(own[E - 1 - t].x)));
+      m.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(own[E - 1 - t].y)));
+      if (j0 == 0) m = own[E - t];
+      reg[t] = cmul(reg[t], m);
     }
+  } else {
+#pragma unroll
+    for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], transfer<M, CONJ>(a.zrev, base, j0 + P * t));
   }
   fft<M, true, false>(reg, lds, j0, a.tw);
   wave_sync();
@@ -434,33 +448,51 @@ hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_bloc
   }
 }
 
-template <int M, int PAD, int TX>
-static hipError_t col_dispatch_conj(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
+// Column-pass variants (all give the same results bit for bit):
+//   0: 8-column tiles, 1: 16-column tiles, 2: 8-column tiles + mirrored H rows,
+//   3: 16-column tiles + mirrored H rows.
+// Tiles must be whole wavefronts: with fewer than 8 lanes per transform, 8-column tiles
+// fall back to 16 columns.
+const char* const kColVariantNames[kColVariants] = {"tile8", "tile16", "tile8+mirror",
+                                                    "tile16+mirror"};
+
+// built-in choice when no variant is forced and no autotuning is asked for
+int default_col_variant(int M) { return M >= 512 ? 0 : 1; }
+
+template <int M, int PAD, int TX, bool MIRROR>
+static hipError_t col_launch(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
   dim3 grid(M / TX, w_count);
   if (conj)
-    col_kernel<M, PAD, true, TX><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+    col_kernel<M, PAD, true, TX, MIRROR><<<grid, TX * Geo<M>::P, 0, s>>>(a);
   else
-    col_kernel<M, PAD, false, TX><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+    col_kernel<M, PAD, false, TX, MIRROR><<<grid, TX * Geo<M>::P, 0, s>>>(a);
   return hipGetLastError();
 }
 
+template <int M, int PAD>
+static hipError_t col_dispatch_variant(int variant, bool conj, const ColArgs& a, int w_count,
+                                       hipStream_t s) {
+  const bool t8 = (variant == 0 || variant == 2) && 8 * Geo<M>::P >= 64;
+  const bool mirror = variant >= 2;
+  if (t8) return mirror ? col_launch<M, PAD, 8, true>(conj, a, w_count, s)
+                        : col_launch<M, PAD, 8, false>(conj, a, w_count, s);
+  return mirror ? col_launch<M, PAD, 16, true>(conj, a, w_count, s)
+                : col_launch<M, PAD, 16, false>(conj, a, w_count, s);
+}
+
 template <int M>
-static hipError_t col_dispatch(int pad, bool conj, int tx, const ColArgs& a, int w_count,
+static hipError_t col_dispatch(int pad, bool conj, int variant, const ColArgs& a, int w_count,
                                hipStream_t s) {
-  // TX columns per block must make whole wavefronts
-  if (tx == 8 && 8 * Geo<M>::P >= 64) {
-    if (pad == 2) return col_dispatch_conj<M, 2, 8>(conj, a, w_count, s);
-    if (pad == 1) return col_dispatch_conj<M, 1, 8>(conj, a, w_count, s);
-  } else {
-    if (pad == 2) return col_dispatch_conj<M, 2, 16>(conj, a, w_count, s);
-    if (pad == 1) return col_dispatch_conj<M, 1, 16>(conj, a, w_count, s);
-  }
+  if (pad == 2) return col_dispatch_variant<M, 2>(variant, conj, a, w_count, s);
+  if (pad == 1) return col_dispatch_variant<M, 1>(variant, conj, a, w_count, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_col(int M, int pad, bool conj, int tx, const ColArgs& a, int w_count, hipStream_t s) {
+hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
+                      hipStream_t s) {
+  if (variant < 0 || variant >= kColVariants) return hipErrorInvalidValue;
   switch (M) {
-#define DPX_CASE(m) case m: return col_dispatch<m>(pad, conj, tx, a, w_count, s);
+#define DPX_CASE(m) case m: return col_dispatch<m>(pad, conj, variant, a, w_count, s);
     DPX_FOR_EACH_M(DPX_CASE)
 #undef DPX_CASE
     default:

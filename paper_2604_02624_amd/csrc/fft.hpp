@@ -26,11 +26,18 @@ namespace dpx {
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Complex products are written with explicit fused multiply-adds so that their rounding does
+// not depend on how the compiler contracts the surrounding code: the same operands give the
+// same bits in every kernel variant.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
+}
 // multiply by -i (forward quarter turn) / +i
 __device__ __forceinline__ float2 mul_negi(float2 a) { return make_float2(a.y, -a.x); }
 __device__ __forceinline__ float2 mul_posi(float2 a) { return make_float2(-a.y, a.x); }
@@ -209,24 +216,36 @@ struct DFT {
 // ------------------------------------------------------------------------------------------
 // radix plans: E registers per lane, radices of each stage (all divide E)
 // ------------------------------------------------------------------------------------------
+// SH: the exchange index i is stored at i + (i >> SH) (one padding slot every 2^SH entries),
+// RX / CX: extra slots between the exchange regions of neighbouring transforms in the row /
+// column kernels.  Chosen with a bank model (64 four-byte banks, 8-byte accesses) so that
+// the scattered stage writes, the strided reads and the column kernel's tile transposes
+// touch each bank about as often as a conflict-free access would.
 template <int M>
 struct Plan;
-template <> struct Plan<64>   { static constexpr int E = 16, NST = 2; static constexpr int R[4] = {16, 4, 0, 0}; };
-template <> struct Plan<96>   { static constexpr int E = 24, NST = 3; static constexpr int R[4] = {3, 8, 4, 0}; };
-template <> struct Plan<128>  { static constexpr int E = 16, NST = 2; static constexpr int R[4] = {16, 8, 0, 0}; };
-template <> struct Plan<192>  { static constexpr int E = 24, NST = 3; static constexpr int R[4] = {3, 8, 8, 0}; };
-template <> struct Plan<256>  { static constexpr int E = 16, NST = 2; static constexpr int R[4] = {16, 16, 0, 0}; };
-template <> struct Plan<384>  { static constexpr int E = 24, NST = 3; static constexpr int R[4] = {6, 8, 8, 0}; };
-template <> struct Plan<512>  { static constexpr int E = 16, NST = 3; static constexpr int R[4] = {8, 8, 8, 0}; };
-template <> struct Plan<1024> { static constexpr int E = 16, NST = 3; static constexpr int R[4] = {16, 16, 4, 0}; };
+template <> struct Plan<64>   { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {16, 4, 0, 0}; };
+template <> struct Plan<96>   { static constexpr int E = 24, NST = 3, SH = 6, RX = 1, CX = 1;  static constexpr int R[4] = {3, 8, 4, 0}; };
+template <> struct Plan<128>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {16, 8, 0, 0}; };
+template <> struct Plan<192>  { static constexpr int E = 24, NST = 3, SH = 3, RX = 4, CX = 4;  static constexpr int R[4] = {3, 8, 8, 0}; };
+template <> struct Plan<256>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 8;  static constexpr int R[4] = {16, 16, 0, 0}; };
+template <> struct Plan<384>  { static constexpr int E = 24, NST = 3, SH = 3, RX = 8, CX = 8;  static constexpr int R[4] = {6, 8, 8, 0}; };
+template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX = 16, CX = 16; static constexpr int R[4] = {8, 8, 8, 0}; };
+template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 5, RX = 0, CX = 4;  static constexpr int R[4] = {16, 16, 4, 0}; };
 
 template <int M>
 struct Geo {
   static constexpr int E = Plan<M>::E;
   static constexpr int P = M / E;  // lanes per transform
+  static constexpr int ROW_REGION = M + (M >> Plan<M>::SH) + Plan<M>::RX;
+  static constexpr int COL_REGION = M + (M >> Plan<M>::SH) + Plan<M>::CX;
   static_assert(P <= 64, "one transform must fit in a wavefront");
   static_assert(64 % P == 0, "transforms must tile a wavefront");
 };
+
+template <int M>
+__device__ __forceinline__ int lds_slot(int i) {
+  return i + (i >> Plan<M>::SH);
+}
 
 // LDS ordering between the lanes of one transform.  A transform never spans more than one
 // wavefront, and a wavefront's LDS instructions execute in program order, so a wave-level
@@ -237,13 +256,23 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr bool divides_or_multiple(int a, int b) { return a % b == 0 || b % a == 0; }
+
 // One Stockham stage: radix R, NS = product of the radices of the earlier stages.
+// Exchange addresses are padded (lds_slot).  When NS and NS*R are both divisors or multiples
+// of the padding period 2^SH, the padded address of output r splits exactly into a per-lane
+// base plus a compile-time offset, and the reads j0 + P t split the same way when P is a
+// multiple of 2^SH; the other stages compute the padded address directly.
 template <int M, int R, int NS, bool LAST, bool INV, bool HALF>
 __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds,
                                                int j0, const float2* __restrict__ tw) {
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
   constexpr int S = E / R;
+  constexpr int SH = Plan<M>::SH;
+  constexpr int S2 = 1 << SH;
+  constexpr bool LIN_W = divides_or_multiple(NS, S2) && divides_or_multiple(NS * R, S2);
+  constexpr bool LIN_R = (P % S2 == 0);
   static_assert(E % R == 0, "radix must divide the registers per lane");
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -256,9 +285,8 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
       constexpr int STRIDE = M / (NS * R);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * k * STRIDE];
-        if constexpr (INV) w.y = -w.y;
-        v[r] = cmul(v[r], w);
+        const float2 w = tw[r * k * STRIDE];
+        v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
       }
     }
     DFT<R, INV, HALF>::run(v);
@@ -266,15 +294,27 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
 #pragma unroll
       for (int r = 0; r < R; ++r) reg[s + r * S] = v[r];
     } else {
-      const int base = (j / NS) * NS * R + k;
+      const int b0 = (j / NS) * NS * R;
+      if constexpr (LIN_W) {
+        const int lane_base = b0 + (b0 >> SH) + k + (k >> SH);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[base + r * NS] = v[r];
+        for (int r = 0; r < R; ++r) lds[lane_base + r * NS + ((r * NS) >> SH)] = v[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lds_slot<M>(b0 + k + r * NS)] = v[r];
+      }
     }
   }
   if constexpr (!LAST) {
     wave_sync();
+    if constexpr (LIN_R) {
+      const int rb = j0 + (j0 >> SH);
 #pragma unroll
-    for (int t = 0; t < E; ++t) reg[t] = lds[j0 + P * t];
+      for (int t = 0; t < E; ++t) reg[t] = lds[rb + P * t + ((P * t) >> SH)];
+    } else {
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = lds[lds_slot<M>(j0 + P * t)];
+    }
     wave_sync();
   }
 }
@@ -296,6 +336,10 @@ template <int M, bool INV, bool HALF>
 __device__ __forceinline__ void fft(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
                                     const float2* __restrict__ tw) {
   constexpr bool H = HALF && (Plan<M>::R[0] % 2 == 0);
+  // Twiddles are re-read by every transform instead of being kept in registers across
+  // transforms (the fence stops the compiler from merging the loads); this keeps the live
+  // register set to one transform's worth.
+  __asm__ volatile("" ::: "memory");
   if constexpr (HALF && !H) {
 #pragma unroll
     for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);

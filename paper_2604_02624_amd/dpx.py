@@ -77,6 +77,12 @@ def load_library(path: str = LIB_PATH):
     for f in ("dpx_plan_create", "dpx_plan_query", "dpx_plan_destroy", "dpx_plan_layout",
               "dpx_plan_sizes", "dpx_forward", "dpx_loss", "dpx_backward"):
         getattr(lib, f).restype = ctypes.c_int
+    lib.dpx_variant_count.argtypes = []
+    lib.dpx_variant_count.restype = i32
+    lib.dpx_variant_name.argtypes = [i32]
+    lib.dpx_variant_name.restype = ctypes.c_char_p
+    lib.dpx_plan_variant.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.dpx_plan_variant.restype = ctypes.c_int
     lib.dpx_timing_enable.argtypes = [vp, i32]
     lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
@@ -116,12 +122,14 @@ def _c_designs(designs):
     return arr, keep
 
 
-def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0):
+def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
+          autotune=0):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
     o.wl_chunk = wl_chunk
     o.force_variant = force_variant
+    o.autotune = int(autotune)
     o.max_workspace_bytes = max_workspace_bytes
     return o
 
@@ -134,6 +142,11 @@ def plan_query(designs, **opts) -> int:
     out = ctypes.c_int64(0)
     _check(lib, lib.dpx_plan_query(arr, len(designs), ctypes.byref(o), ctypes.byref(out)))
     return int(out.value)
+
+
+def variant_names():
+    lib = load_library()
+    return [lib.dpx_variant_name(i).decode() for i in range(lib.dpx_variant_count())]
 
 
 def _ptr(t):
@@ -152,14 +165,14 @@ class Plan:
     device, packed over designs as the C ABI describes."""
 
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
-                 force_variant: int = -1, max_workspace_bytes: int = 0):
+                 force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
         self.lib = load_library()
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
-        o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes)
+        o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))
@@ -181,6 +194,11 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def variant(self, i: int = 0) -> int:
+        v = ctypes.c_int32()
+        _check(self.lib, self.lib.dpx_plan_variant(self._h, i, ctypes.byref(v)))
+        return v.value
 
     def layout(self, i: int) -> dict:
         lo = CLayout()

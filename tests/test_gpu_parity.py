@@ -280,17 +280,39 @@ def test_bitwise_repeatable_and_batch_invariant(torch_dev):
 
 
 def test_recompute_mode_and_column_variants_agree(torch_dev):
-    say("store vs recompute mode, column tile 8 vs 16")
+    say("store vs recompute mode; every column-pass variant; autotuned plan")
+    from paper_2604_02624_amd import dpx
     w = wk.make_workload(3)
     d, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
     base = run_gpu(torch_dev, [d], [h], [tau])
     rec = run_gpu(torch_dev, [d], [h], [tau], checkpoint_mode=1, wl_chunk=48)
     assert torch_dev.equal(rec["I"], base["I"])
     assert rel_l2(rec["dh"].cpu().numpy(), base["dh"].cpu().numpy()) <= 1e-6
-    for tx in (8, 16):
-        v = run_gpu(torch_dev, [d], [h], [tau], force_variant=tx)
-        assert torch_dev.equal(v["I"], base["I"])
-        assert torch_dev.equal(v["dh"], base["dh"])
+    for v in range(len(dpx.variant_names())):
+        r = run_gpu(torch_dev, [d], [h], [tau], force_variant=v)
+        assert r["plan"].variant(0) == v
+        assert torch_dev.equal(r["I"], base["I"]), dpx.variant_names()[v]
+        assert torch_dev.equal(r["dh"], base["dh"]), dpx.variant_names()[v]
+    at = run_gpu(torch_dev, [d], [h], [tau], autotune=True)
+    say(f"autotuned variant {dpx.variant_names()[at['plan'].variant(0)]}")
+    assert torch_dev.equal(at["I"], base["I"])
+
+
+def test_variants_agree_on_every_transform_length(torch_dev):
+    say("column-pass variants, pad 2, N in {48, 96, 192}")
+    from paper_2604_02624_amd import dpx
+    for n in (48, 96, 192):
+        g = np.random.default_rng(300 + n)
+        wl = np.array([450e-9, 600e-9, 750e-9])
+        d = wk.make_design(n=n, layers=2, wl=wl, n_mat=1.5, dx=300e-9, z=[20e-6, 30e-6],
+                           fov=n // 2, pad=2)
+        h = (g.random((2, n, n)) * 1.2e-6).astype(np.float32)
+        tau = g.random((3, n // 2, n // 2)).astype(np.float32)
+        outs = [run_gpu(torch_dev, [d], [h], [tau], force_variant=v)
+                for v in range(len(dpx.variant_names()))]
+        for r in outs[1:]:
+            assert torch_dev.equal(r["I"], outs[0]["I"])
+            assert torch_dev.equal(r["dh"], outs[0]["dh"])
 
 
 def test_error_paths(torch_dev):
