@@ -529,19 +529,17 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     }
     p->bytes += d.bytes;
     if (!p->twiddles.count(d.M)) {
-      std::vector<float2> tw(d.M);
-      for (int m = 0; m < d.M; ++m) {
-        const double ang = kTwoPi * static_cast<double>(m) / static_cast<double>(d.M);
-        tw[m] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(-std::sin(ang)));
-      }
+      std::vector<float2> tw;
+      dpx::build_twiddle_table(d.M, tw);
       float2* dtw = nullptr;
-      if ((st = dev_alloc(&dtw, static_cast<int64_t>(d.M) * 8, "twiddles")) != DPX_OK) break;
+      const int64_t tb = static_cast<int64_t>(tw.size()) * 8;
+      if ((st = dev_alloc(&dtw, tb, "twiddles")) != DPX_OK) break;
       p->twiddles[d.M] = dtw;
-      if (hipMemcpy(dtw, tw.data(), d.M * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+      if (hipMemcpy(dtw, tw.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
         st = fail(DPX_E_DEVICE, "copy of the twiddle table failed");
         break;
       }
-      p->bytes += static_cast<int64_t>(d.M) * 8;
+      p->bytes += tb;
     }
   }
   if (st == DPX_OK && o.autotune && o.force_variant < 0) {

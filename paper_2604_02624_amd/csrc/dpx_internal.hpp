@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace dpx {
 
@@ -36,7 +37,7 @@ struct RowArgs {
   const float* dl_di;        // [W][T][T] (global w)
   float* dh_part;            // [nchunk][K][N][N] per-chunk dL/dh partial sums
   const WlConst* wl;         // [W] (global w)
-  const float2* tw;          // [M] twiddles
+  const float2* tw;          // per-stage twiddle table of the transform length
   int n, fov, bin, layer, layers;
   int row_lo, row_hi;        // rows this pass processes
   int w_begin, w_count;      // global wavelength range of this launch (chunk)
@@ -50,7 +51,7 @@ struct RowArgs {
 struct ColArgs {
   float2* spec;              // [wc][N][M]
   const WlConst* wl;         // [W] (global w)
-  const float2* tw;          // [M]
+  const float2* tw;          // per-stage twiddle table of the transform length
   double zrev;               // z / (M dx): revolutions per unit of sqrt(q)
   int n;
   int in_lo, in_hi;          // rows holding non-zero input (others read as zero)
@@ -76,6 +77,8 @@ hipError_t launch_dh_reduce(const float* part, float* dh, int nchunk, int64_t pe
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 
 bool fft_size_supported(int M);
+// host: per-stage twiddle table of the length-M transform (layout in fft.hpp)
+void build_twiddle_table(int M, std::vector<float2>& out);
 int row_lanes_per_transform(int M);  // P = M / E
 
 }  // namespace dpx

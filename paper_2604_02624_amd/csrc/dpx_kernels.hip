@@ -8,6 +8,9 @@
 // and the next row pass starts with the inverse transform along x.  Zero padding is placed
 // at the high end of each axis instead of centring it: a circular convolution commutes with
 // shifts, so cropping the same corner returns the same N x N field.
+#include <cmath>
+#include <vector>
+
 #include "dpx_internal.hpp"
 #include "fft.hpp"
 #include "phase.hpp"
@@ -41,6 +44,9 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
   constexpr bool HALF = (PAD == 2);
   constexpr int RG = Geo<M>::ROW_REGION;
   __shared__ float2 lds_all[G * RG];
+  __shared__ float2 tw[twiddle_count<M>()];
+  stage_twiddles<M>(tw, a.tw, threadIdx.x, kRowThreads);
+  __syncthreads();
 
   const int N = M / PAD;
   const int g = threadIdx.x / P;
@@ -79,7 +85,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
       }
-      fft<M, false, HALF>(reg, lds, j0, a.tw);
+      fft<M, false, HALF>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
 #pragma unroll
@@ -94,7 +100,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false>(reg, lds, j0, a.tw);
+      fft<M, true, false>(reg, lds, j0, tw);
 #pragma unroll
       for (int t = 0; t < EN; ++t) reg[t] = cmul(reg[t], transmission(hreg[t], c));
       if (a.store_ckpt && active) {
@@ -103,7 +109,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
       }
-      fft<M, false, HALF>(reg, lds, j0, a.tw);
+      fft<M, false, HALF>(reg, lds, j0, tw);
       if (active) {
 #pragma unroll
         for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
@@ -118,7 +124,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false>(reg, lds, j0, a.tw);
+      fft<M, true, false>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.ofov + static_cast<size_t>(wc) * F * F + static_cast<size_t>(y - x0) * F;
 #pragma unroll
@@ -146,7 +152,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
           reg[t] = make_float2(0.f, 0.f);
         }
       }
-      fft<M, false, HALF>(reg, lds, j0, a.tw);
+      fft<M, false, HALF>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
 #pragma unroll
@@ -166,7 +172,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false>(reg, lds, j0, a.tw);
+      fft<M, true, false>(reg, lds, j0, tw);
       const float ct = static_cast<float>(c.ct);
       const float ca = static_cast<float>(c.ca);
 #pragma unroll
@@ -180,7 +186,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
         if constexpr (MODE == ROW_ADJ_MID) reg[t] = cmulc(gv, transmission(hreg[t], c));
       }
       if constexpr (MODE == ROW_ADJ_MID) {
-        fft<M, false, HALF>(reg, lds, j0, a.tw);
+        fft<M, false, HALF>(reg, lds, j0, tw);
         if (active) {
 #pragma unroll
           for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
@@ -227,9 +233,18 @@ col_kernel(ColArgs a) {
   constexpr int EN = E / PAD;
   constexpr bool HALF = (PAD == 2);
   __shared__ float2 tile[TX * LD];
+  __shared__ float2 tw[twiddle_count<M>()];
 
   const int N = M / PAD;
-  const int kx0 = blockIdx.x * TX;
+  // XCD-aware tile order: consecutive blocks go to the eight XCDs in turn, so blocks b and
+  // b + 8 of every run of 16 share an XCD and its L2; giving them neighbouring column tiles
+  // lets the two halves of each 128-byte row segment meet in the same L2.
+  int tile_x = blockIdx.x;
+  if ((gridDim.x & 15) == 0) {
+    const int r = tile_x & 15;
+    tile_x = (tile_x & ~15) + ((r & 7) << 1) + (r >> 3);
+  }
+  const int kx0 = tile_x * TX;
   float2* spec = a.spec + static_cast<size_t>(blockIdx.y) * N * M;
   const WlConst c = a.wl[a.w_begin + blockIdx.y];
 
@@ -237,6 +252,7 @@ col_kernel(ColArgs a) {
   const int yy = threadIdx.x / TX;
   for (int y = a.in_lo + yy; y < a.in_hi; y += NT / TX)
     tile[cc * LD + y] = spec[static_cast<size_t>(y) * M + kx0 + cc];
+  stage_twiddles<M>(tw, a.tw, threadIdx.x, NT);
   __syncthreads();
 
   const int g = threadIdx.x / P;
@@ -249,7 +265,7 @@ col_kernel(ColArgs a) {
     reg[t] = (y >= a.in_lo && y < a.in_hi) ? lds[y] : make_float2(0.f, 0.f);
   }
   wave_sync();
-  fft<M, false, HALF>(reg, lds, j0, a.tw);
+  fft<M, false, HALF>(reg, lds, j0, tw);
 
   // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0.
   const int kx = kx0 + g;
@@ -259,27 +275,28 @@ col_kernel(ColArgs a) {
     // H depends on ky^2 only: lane j0 holds ky = j0 + P t, and for t >= E/2 the row M - ky
     // is register E-1-t of lane P - j0 (lane 0 mirrors onto its own register E - t), so
     // each lane evaluates E/2 + 1 rows and fetches the others across lanes.
+    // Streamed so that only two evaluations are live at a time: step u applies row u and the
+    // mirrored row E-1-u (whose value lane 0 takes from its own evaluation u+1).
     constexpr int EH = E / 2;
-    float2 own[EH + 1];
-#pragma unroll
-    for (int t = 0; t <= EH; ++t) own[t] = transfer<M, CONJ>(a.zrev, base, j0 + P * t);
-#pragma unroll
-    for (int t = 0; t < EH; ++t) reg[t] = cmul(reg[t], own[t]);
     const int lane = threadIdx.x & 63;
     const int src = ((lane - j0) + ((P - j0) & (P - 1))) << 2;
+    float2 cur = transfer<M, CONJ>(a.zrev, base, j0);
 #pragma unroll
-    for (int t = EH; t < E; ++t) {
+    for (int u = 0; u < EH; ++u) {
+      const float2 nxt = transfer<M, CONJ>(a.zrev, base, j0 + P * (u + 1));
+      reg[u] = cmul(reg[u], cur);
       float2 m;
-      m.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(own[E - 1 - t].x)));
-      m.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(own[E - 1 - t].y)));
-      if (j0 == 0) m = own[E - t];
-      reg[t] = cmul(reg[t], m);
+      m.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.x)));
+      m.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.y)));
+      if (j0 == 0) m = nxt;
+      reg[E - 1 - u] = cmul(reg[E - 1 - u], m);
+      cur = nxt;
     }
   } else {
 #pragma unroll
     for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], transfer<M, CONJ>(a.zrev, base, j0 + P * t));
   }
-  fft<M, true, false>(reg, lds, j0, a.tw);
+  fft<M, true, false>(reg, lds, j0, tw);
   wave_sync();
 #pragma unroll
   for (int t = 0; t < EN; ++t) {
@@ -415,6 +432,35 @@ static hipError_t row_dispatch_pad(int pad, int mode, const RowArgs& a, dim3 gri
 
 #define DPX_FOR_EACH_M(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
 
+template <int M>
+static void twiddle_table(std::vector<float2>& out) {
+  out.assign(twiddle_count<M>() > 0 ? twiddle_count<M>() : 1, make_float2(1.f, 0.f));
+  int ns = Plan<M>::R[0];
+  for (int st = 1; st < Plan<M>::NST; ++st) {
+    const int R = Plan<M>::R[st];
+    const int L = ns * R;
+    const int off = twiddle_offset<M>(st);
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < ns; ++k) {
+        const double ang = 6.283185307179586476925286766559 * static_cast<double>((r * k) % L) /
+                           static_cast<double>(L);
+        out[off + (r - 1) * ns + k] = make_float2(static_cast<float>(std::cos(ang)),
+                                                  static_cast<float>(-std::sin(ang)));
+      }
+    ns = L;
+  }
+}
+
+void build_twiddle_table(int M, std::vector<float2>& out) {
+  switch (M) {
+#define DPX_CASE(m) case m: twiddle_table<m>(out); return;
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      out.clear();
+  }
+}
+
 bool fft_size_supported(int M) {
   switch (M) {
 #define DPX_CASE(m) case m:
@@ -457,7 +503,7 @@ const char* const kColVariantNames[kColVariants] = {"tile8", "tile16", "tile8+mi
                                                     "tile16+mirror"};
 
 // built-in choice when no variant is forced and no autotuning is asked for
-int default_col_variant(int M) { return M >= 512 ? 0 : 1; }
+int default_col_variant(int M) { return M >= 512 ? 2 : 3; }
 
 template <int M, int PAD, int TX, bool MIRROR>
 static hipError_t col_launch(bool conj, const ColArgs& a, int w_count, hipStream_t s) {

@@ -9,9 +9,10 @@
 // strided natural order it started in, with (#stages - 1) LDS round trips.
 //
 // Forward transforms use exp(-2 pi i k n / M), inverse ones exp(+2 pi i k n / M), both
-// unnormalised.  Inter-stage twiddles come from a table tw[m] = exp(-2 pi i m / M) built on
-// the host in double precision from the exact integer index m; inverse stages conjugate it.
-// Twiddles inside a radix-R butterfly are compile-time constants.
+// unnormalised.  Inter-stage twiddles come from a per-stage table built on the host in double
+// precision from exact integer indices (see twiddle_offset) and staged into LDS by each block;
+// inverse stages conjugate it.  Twiddles inside a radix-R butterfly are compile-time
+// constants.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -242,9 +243,31 @@ struct Geo {
   static_assert(64 % P == 0, "transforms must tile a wavefront");
 };
 
+// Per-stage twiddle table: stage s (radix R, NS = product of the earlier radices, s >= 1)
+// stores W_{NS R}^{r k} = exp(-2 pi i r k / (NS R)) at twiddle_offset(s) + (r - 1) NS + k for
+// r = 1..R-1, k = 0..NS-1, so that the lanes of one butterfly row read consecutive entries.
+template <int M>
+constexpr int twiddle_offset(int stage) {
+  int off = 0, ns = 1;
+  for (int s = 0; s < stage; ++s) {
+    if (s > 0) off += (Plan<M>::R[s] - 1) * ns;
+    ns *= Plan<M>::R[s];
+  }
+  return off;
+}
+template <int M>
+constexpr int twiddle_count() { return twiddle_offset<M>(Plan<M>::NST); }
+
 template <int M>
 __device__ __forceinline__ int lds_slot(int i) {
   return i + (i >> Plan<M>::SH);
+}
+
+// Copies the per-stage twiddle table from global memory into LDS (caller synchronises).
+template <int M>
+__device__ __forceinline__ void stage_twiddles(float2* __restrict__ dst, const float2* __restrict__ src,
+                                               int tid, int nthreads) {
+  for (int i = tid; i < twiddle_count<M>(); i += nthreads) dst[i] = src[i];
 }
 
 // LDS ordering between the lanes of one transform.  A transform never spans more than one
@@ -263,7 +286,7 @@ constexpr bool divides_or_multiple(int a, int b) { return a % b == 0 || b % a ==
 // of the padding period 2^SH, the padded address of output r splits exactly into a per-lane
 // base plus a compile-time offset, and the reads j0 + P t split the same way when P is a
 // multiple of 2^SH; the other stages compute the padded address directly.
-template <int M, int R, int NS, bool LAST, bool INV, bool HALF>
+template <int M, int ST, int R, int NS, bool LAST, bool INV, bool HALF>
 __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds,
                                                int j0, const float2* __restrict__ tw) {
   constexpr int E = Geo<M>::E;
@@ -282,10 +305,10 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = reg[s + r * S];
     if constexpr (NS > 1) {
-      constexpr int STRIDE = M / (NS * R);
+      constexpr int OFF = twiddle_offset<M>(ST);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const float2 w = tw[r * k * STRIDE];
+        const float2 w = tw[OFF + (r - 1) * NS + k];
         v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
       }
     }
@@ -325,21 +348,18 @@ __device__ __forceinline__ void fft_stages(float2 (&reg)[Geo<M>::E], float2* __r
   if constexpr (ST < Plan<M>::NST) {
     constexpr int R = Plan<M>::R[ST];
     constexpr bool LAST = (ST + 1 == Plan<M>::NST);
-    stockham_stage<M, R, NS, LAST, INV, HALF && ST == 0>(reg, lds, j0, tw);
+    stockham_stage<M, ST, R, NS, LAST, INV, HALF && ST == 0>(reg, lds, j0, tw);
     fft_stages<M, ST + 1, NS * R, INV, false>(reg, lds, j0, tw);
   }
 }
 
 // Full length-M transform of the group's registers.  HALF: elements M/2..M-1 are zero
-// (zero-padded input); only used when the first radix is even.
+// (zero-padded input); only used when the first radix is even.  tw: the per-stage twiddle
+// table (in LDS).
 template <int M, bool INV, bool HALF>
 __device__ __forceinline__ void fft(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
                                     const float2* __restrict__ tw) {
   constexpr bool H = HALF && (Plan<M>::R[0] % 2 == 0);
-  // Twiddles are re-read by every transform instead of being kept in registers across
-  // transforms (the fence stops the compiler from merging the loads); this keeps the live
-  // register set to one transform's worth.
-  __asm__ volatile("" ::: "memory");
   if constexpr (HALF && !H) {
 #pragma unroll
     for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);
