@@ -141,6 +141,7 @@ def main():
     ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--checkpoint-mode", type=int, default=0, choices=[0, 1])
     ap.add_argument("--wl-chunk", type=int, default=0)
+    ap.add_argument("--streams", type=int, default=0, help="concurrent chunk lanes (0 automatic)")
     ap.add_argument("--variant", type=int, default=-1, help="column-pass variant (-1 automatic)")
     ap.add_argument("--autotune", action="store_true", help="time column-pass variants at plan creation")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -168,7 +169,7 @@ def main():
     w = wk.make_workload(args.workload)
     designs = w["designs"]
     plan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
-                    force_variant=args.variant, autotune=args.autotune)
+                    force_variant=args.variant, autotune=args.autotune, streams=args.streams)
     variant = dpx.variant_names()[plan.variant(0)]
     log(f"[bench] column-pass variant {variant}")
     h = plan.pack_heights(w["h"])
@@ -257,7 +258,8 @@ def main():
         config=dict(workload=WORKLOAD_NAMES[args.workload], designs=len(designs),
                     wavelengths=sum(d["n_wl"] for d in designs), layers=d0["layers"], n=d0["n"],
                     transform=d0["n"] * d0["pad"], checkpoint_mode=args.checkpoint_mode,
-                    wl_chunk=args.wl_chunk, column_variant=variant, phase_args="f64"),
+                    wl_chunk=args.wl_chunk, streams=args.streams, column_variant=variant,
+                    phase_args="f64"),
         roofline=roofline, cpu_baseline=cpu, plain_loop=plain,
         vs_plain_loop=(round(value / plain["value"], 2) if plain else None),
         passes=pass_summary, wall_s=round(wall, 3),

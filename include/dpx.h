@@ -91,7 +91,7 @@ typedef struct dpx_opts {
   int32_t checkpoint_mode;  /* 0: forward stores the field after every transmission
                                (K*W*N*N complex per design) for the backward;
                                1: backward recomputes the forward chunk by chunk */
-  int32_t wl_chunk;         /* wavelengths per recompute chunk (0 = automatic) */
+  int32_t wl_chunk;         /* wavelengths per chunk (0 = automatic) */
   int32_t use_graph;        /* reserved: capture launch sequences in HIP graphs */
   int32_t autotune;         /* nonzero: dpx_plan_create times every column-pass variant on
                                each distinct transform length and keeps the fastest */
@@ -102,6 +102,11 @@ typedef struct dpx_opts {
   int32_t check_finite;     /* reserved */
   int64_t max_workspace_bytes; /* 0 = no limit; otherwise plan creation fails with
                                   DPX_E_NOMEM if the plan would need more */
+  int32_t streams;          /* wavelength chunks processed concurrently on this many streams
+                               (the caller's plus streams the plan owns); 0 = automatic (1).
+                               The dL/dh summation order follows the lane layout, so results
+                               agree to rounding across settings and bit for bit per setting. */
+  int32_t reserved;
 } dpx_opts;
 
 /* Offsets (in elements of the buffer's type) of one design inside the packed buffers. */

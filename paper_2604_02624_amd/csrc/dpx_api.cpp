@@ -52,9 +52,12 @@ struct Design {
   std::vector<double> wl, n_mat, kappa, z;
   int64_t h_off, u_off, img_off;
   // launch geometry
-  int wl_chunk;      // wavelengths per chunk (spec buffer depth)
+  int wl_chunk;      // wavelengths per chunk (spec buffer depth per lane)
+  int nchunks;       // ceil(W / wl_chunk)
+  int lanes;         // chunks run on this many streams at once (chunk c on lane c % lanes)
   int w_per_block;   // wavelengths per row-pass block
-  int nslots;        // dL/dh partial slots = ceil(wl_chunk / w_per_block)
+  int slots_per_lane;  // dL/dh partial slots of one lane = ceil(wl_chunk / w_per_block)
+  int nslots;        // lanes * slots_per_lane
   int row_group;     // rows per row-pass block
   int col_variant;   // column-pass kernel variant
   // device memory
@@ -83,6 +86,9 @@ struct PassTotals {
 
 struct dpx_plan {
   std::vector<Design> designs;
+  std::vector<hipStream_t> aux;   // lanes 1..L-1 (lane 0 is the caller's stream)
+  hipEvent_t ev_fork = nullptr, ev_offset = nullptr;
+  std::vector<hipEvent_t> ev_join;
   bool timing = false;
   std::vector<TimedLaunch> pending;
   PassTotals totals[DPX_PASS_COUNT];
@@ -106,6 +112,7 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
     if (o->checkpoint_mode != 0 && o->checkpoint_mode != 1)
       return fail(DPX_E_ARG, "checkpoint_mode must be 0 or 1");
     if (o->wl_chunk < 0) return fail(DPX_E_ARG, "wl_chunk must be >= 0");
+    if (o->streams < 0 || o->streams > 8) return fail(DPX_E_ARG, "streams must be in [0, 8]");
     if (o->max_workspace_bytes < 0) return fail(DPX_E_ARG, "max_workspace_bytes must be >= 0");
     if (o->force_variant < -1 || o->force_variant >= dpx::kColVariants)
       return fail(DPX_E_ARG, "force_variant must be -1 or a variant index below %d", dpx::kColVariants);
@@ -155,12 +162,22 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   d.dx = src.dx;
   d.n_m = src.n_medium;
   const int P = dpx::row_lanes_per_transform(d.M);
-  d.row_group = 256 / P;
+  (void)P;
+  d.row_group = dpx::row_rows_per_block(d.M, dpx::ROW_FWD_MID);
   const int row_blocks = (d.N + d.row_group - 1) / d.row_group;
   // wavelengths per chunk: everything at once unless asked otherwise (recompute mode
   // defaults to chunks of 64)
-  int chunk = o.wl_chunk > 0 ? o.wl_chunk : (o.checkpoint_mode == 1 ? 64 : d.W);
-  chunk = std::min(chunk, d.W);
+  // concurrent lanes: chunks of wavelengths on several streams, so that one chunk's column
+  // pass (arithmetic-bound) can run beside another chunk's row pass (memory-bound)
+  const int64_t work = static_cast<int64_t>(d.W) * d.N * d.M;
+  // (measured on the large workload: two lanes share the chip without shortening the step,
+  // so the automatic choice is one lane; more lanes remain available on request)
+  (void)work;
+  const int lanes_wanted = o.streams > 0 ? o.streams : 1;
+  int chunk = o.wl_chunk > 0 ? o.wl_chunk
+                             : (o.checkpoint_mode == 1 ? 64 : (d.W + 2 * lanes_wanted - 1) / (2 * lanes_wanted));
+  if (lanes_wanted == 1 && o.wl_chunk <= 0 && o.checkpoint_mode == 0) chunk = d.W;
+  chunk = std::max(1, std::min(chunk, d.W));
   // wavelengths per row-pass block: enough blocks to fill the chip (about 2048), at most 16
   int wpb = static_cast<int>(std::max<int64_t>(1, static_cast<int64_t>(chunk) * row_blocks / 2048));
   wpb = std::min(wpb, 16);
@@ -169,13 +186,16 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
     chunk = std::max(wpb, chunk / wpb * wpb);
   }
   d.wl_chunk = chunk;
+  d.nchunks = (d.W + chunk - 1) / chunk;
+  d.lanes = std::max(1, std::min(lanes_wanted, d.nchunks));
   d.w_per_block = wpb;
-  d.nslots = (chunk + wpb - 1) / wpb;
+  d.slots_per_lane = (chunk + wpb - 1) / wpb;
+  d.nslots = d.lanes * d.slots_per_lane;
   d.col_variant = o.force_variant >= 0 ? o.force_variant : dpx::default_col_variant(d.M);
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
-  const int ck_w = (o.checkpoint_mode == 1) ? chunk : d.W;
-  const int of_w = (o.checkpoint_mode == 1) ? chunk : d.W;
-  d.bytes = static_cast<int64_t>(chunk) * d.N * d.M * 8      // spec
+  const int ck_w = (o.checkpoint_mode == 1) ? d.lanes * d.wl_chunk : d.W;
+  const int of_w = ck_w;
+  d.bytes = static_cast<int64_t>(d.lanes) * d.wl_chunk * d.N * d.M * 8  // spec
             + static_cast<int64_t>(d.K) * ck_w * nn * 8       // checkpoints
             + static_cast<int64_t>(of_w) * d.F * d.F * 8      // output field
             + static_cast<int64_t>(d.nslots) * d.K * nn * 4   // dL/dh partials
@@ -234,7 +254,12 @@ dpx_status sticky_check() {
     if (s_ != DPX_OK) return s_;        \
   } while (0)
 
-RowArgs row_args(const dpx_plan* p, const Design& d, int w0, int wc) {
+float2* spec_of_lane(const Design& d, int lane) {
+  return d.spec + static_cast<int64_t>(lane) * d.wl_chunk * d.N * d.M;
+}
+
+// launch arguments for chunk [w0, w0 + wc) running on lane `lane`
+RowArgs row_args(const dpx_plan* p, const Design& d, int w0, int wc, int lane) {
   RowArgs a{};
   a.wl = d.d_wl;
   a.tw = p->twiddles.at(d.M);
@@ -245,13 +270,13 @@ RowArgs row_args(const dpx_plan* p, const Design& d, int w0, int wc) {
   a.w_begin = w0;
   a.w_count = wc;
   a.w_per_block = d.w_per_block;
-  a.chunk_base = 0;
-  a.spec = d.spec;
+  a.chunk_base = lane * d.slots_per_lane;
+  a.spec = spec_of_lane(d, lane);
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
   if (p->opts.checkpoint_mode == 1) {
-    a.ckpt = d.ckpt;
+    a.ckpt = d.ckpt + static_cast<int64_t>(lane) * d.K * d.wl_chunk * nn;
     a.ckpt_w_stride = d.wl_chunk;
-    a.ofov = d.ofov;
+    a.ofov = d.ofov + static_cast<int64_t>(lane) * d.wl_chunk * d.F * d.F;
   } else {
     a.ckpt = d.ckpt + w0 * nn;
     a.ckpt_w_stride = d.W;
@@ -296,7 +321,8 @@ int64_t row_bytes(const Design& d, int mode, int wc, int nwb, bool accumulate, b
 dpx_status run_row(dpx_plan* p, const Design& d, int mode, RowArgs a, int row_lo, int row_hi, hipStream_t s) {
   a.row_lo = row_lo;
   a.row_hi = row_hi;
-  const int nrb = (row_hi - row_lo + d.row_group - 1) / d.row_group;
+  const int rg = dpx::row_rows_per_block(d.M, mode);
+  const int nrb = (row_hi - row_lo + rg - 1) / rg;
   const int nwb = (a.w_count + d.w_per_block - 1) / d.w_per_block;
   TimedLaunch t{DPX_PASS_ROW_FWD_FIRST + mode, nullptr, nullptr,
                 row_bytes(d, mode, a.w_count, nwb, a.accumulate != 0, a.u_in != nullptr)};
@@ -307,10 +333,10 @@ dpx_status run_row(dpx_plan* p, const Design& d, int mode, RowArgs a, int row_lo
   return DPX_OK;
 }
 
-dpx_status run_col(dpx_plan* p, const Design& d, int layer, bool conj, int w0, int wc,
+dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj, int w0, int wc,
                    int in_lo, int in_hi, int out_lo, int out_hi, hipStream_t s) {
   ColArgs c{};
-  c.spec = d.spec;
+  c.spec = spec_of_lane(d, lane);
   c.wl = d.d_wl;
   c.tw = p->twiddles.at(d.M);
   c.zrev = d.z[layer] / (static_cast<double>(d.M) * d.dx);
@@ -331,19 +357,21 @@ dpx_status run_col(dpx_plan* p, const Design& d, int layer, bool conj, int w0, i
 
 int64_t h_off_layer(const Design& d, int l) { return d.h_off + static_cast<int64_t>(l) * d.N * d.N; }
 
-// forward over one chunk of wavelengths [w0, w0 + wc); leaves the output field in ofov
+// forward over one chunk of wavelengths [w0, w0 + wc) on lane `lane`; leaves the output
+// field in ofov.  `after_first` (may be null) is recorded on s after the first launch.
 dpx_status forward_chunk(dpx_plan* p, const Design& d, const float* h, const float* u_in,
-                         int w0, int wc, hipStream_t s) {
+                         int w0, int wc, int lane, hipStream_t s, hipEvent_t after_first) {
   const int fo = (d.N - d.F) / 2;
-  RowArgs a = row_args(p, d, w0, wc);
+  RowArgs a = row_args(p, d, w0, wc, lane);
   a.u_in = u_in ? reinterpret_cast<const float2*>(u_in) + d.u_off : nullptr;
   a.store_ckpt = 1;
   a.layer = 0;
   a.h = h + h_off_layer(d, 0);
   DPX_TRY(run_row(p, d, dpx::ROW_FWD_FIRST, a, 0, d.N, s));
+  if (after_first) DPX_HIP(hipEventRecord(after_first, s));
   for (int l = 0; l < d.K; ++l) {
     const bool last = (l == d.K - 1);
-    DPX_TRY(run_col(p, d, l, false, w0, wc, 0, d.N, last ? fo : 0, last ? fo + d.F : d.N, s));
+    DPX_TRY(run_col(p, d, lane, l, false, w0, wc, 0, d.N, last ? fo : 0, last ? fo + d.F : d.N, s));
     if (!last) {
       a.layer = l + 1;
       a.h = h + h_off_layer(d, l + 1);
@@ -355,20 +383,44 @@ dpx_status forward_chunk(dpx_plan* p, const Design& d, const float* h, const flo
   return DPX_OK;
 }
 
+// adjoint over one chunk on lane `lane`; dL/dh partials go to the lane's own slots, added to
+// what the lane's earlier chunks left there when `accumulate` is set
 dpx_status adjoint_chunk(dpx_plan* p, const Design& d, const float* h, const float* dl_di,
-                         int w0, int wc, bool accumulate_first, hipStream_t s) {
+                         int w0, int wc, int lane, bool accumulate, hipStream_t s,
+                         hipEvent_t after_first) {
   const int fo = (d.N - d.F) / 2;
-  RowArgs a = row_args(p, d, w0, wc);
+  RowArgs a = row_args(p, d, w0, wc, lane);
   a.dl_di = dl_di + d.img_off;
   a.store_ckpt = 0;
-  a.accumulate = accumulate_first ? 1 : 0;
+  a.accumulate = accumulate ? 1 : 0;
   DPX_TRY(run_row(p, d, dpx::ROW_ADJ_SEED, a, fo, fo + d.F, s));
+  if (after_first) DPX_HIP(hipEventRecord(after_first, s));
   for (int l = d.K - 1; l >= 0; --l) {
     const bool first = (l == d.K - 1);
-    DPX_TRY(run_col(p, d, l, true, w0, wc, first ? fo : 0, first ? fo + d.F : d.N, 0, d.N, s));
+    DPX_TRY(run_col(p, d, lane, l, true, w0, wc, first ? fo : 0, first ? fo + d.F : d.N, 0, d.N, s));
     a.layer = l;
     a.h = h + h_off_layer(d, l);
     DPX_TRY(run_row(p, d, l > 0 ? dpx::ROW_ADJ_MID : dpx::ROW_ADJ_LAST, a, 0, d.N, s));
+  }
+  return DPX_OK;
+}
+
+// Chunk c of a design runs on lane c % lanes.  Lane 0 is the caller's stream; the other
+// lanes fork from it, start one pass behind lane 0 (so that the column pass of one chunk
+// meets the row pass of another), and join back before the call returns.
+hipStream_t lane_stream(dpx_plan* p, int lane, hipStream_t s) { return lane == 0 ? s : p->aux[lane - 1]; }
+
+dpx_status fork_lanes(dpx_plan* p, const Design& d, hipStream_t s) {
+  if (d.lanes <= 1) return DPX_OK;
+  DPX_HIP(hipEventRecord(p->ev_fork, s));
+  for (int l = 1; l < d.lanes; ++l) DPX_HIP(hipStreamWaitEvent(p->aux[l - 1], p->ev_fork, 0));
+  return DPX_OK;
+}
+
+dpx_status join_lanes(dpx_plan* p, const Design& d, hipStream_t s) {
+  for (int l = 1; l < d.lanes; ++l) {
+    DPX_HIP(hipEventRecord(p->ev_join[l - 1], p->aux[l - 1]));
+    DPX_HIP(hipStreamWaitEvent(s, p->ev_join[l - 1], 0));
   }
   return DPX_OK;
 }
@@ -394,9 +446,9 @@ dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
   p->timing = false;
   for (int v = 0; v < dpx::kColVariants; ++v) {
     d.col_variant = v;
-    DPX_TRY(run_col(p, d, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
+    DPX_TRY(run_col(p, d, 0, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
     DPX_HIP(hipEventRecord(e0, nullptr));
-    for (int r = 0; r < 3; ++r) DPX_TRY(run_col(p, d, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
+    for (int r = 0; r < 3; ++r) DPX_TRY(run_col(p, d, 0, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
     DPX_HIP(hipEventRecord(e1, nullptr));
     DPX_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -516,9 +568,9 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
       tab[w].ct = kTwoPi * (d.n_mat[w] - d.n_m) / lam;
     }
     const int64_t nn = static_cast<int64_t>(d.N) * d.N;
-    const int ck_w = (o.checkpoint_mode == 1) ? d.wl_chunk : d.W;
+    const int ck_w = (o.checkpoint_mode == 1) ? d.lanes * d.wl_chunk : d.W;
     if ((st = dev_alloc(&d.d_wl, d.W * sizeof(WlConst), "wavelength table")) != DPX_OK) break;
-    if ((st = dev_alloc(&d.spec, static_cast<int64_t>(d.wl_chunk) * d.N * d.M * 8, "spectra")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.spec, static_cast<int64_t>(d.lanes) * d.wl_chunk * d.N * d.M * 8, "spectra")) != DPX_OK) break;
     if ((st = dev_alloc(&d.ckpt, static_cast<int64_t>(d.K) * ck_w * nn * 8, "checkpoints")) != DPX_OK) break;
     if ((st = dev_alloc(&d.ofov, static_cast<int64_t>(ck_w) * d.F * d.F * 8, "output field")) != DPX_OK) break;
     if ((st = dev_alloc(&d.dh_part, static_cast<int64_t>(d.nslots) * d.K * nn * 4, "gradient partials")) != DPX_OK) break;
@@ -540,6 +592,26 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
         break;
       }
       p->bytes += tb;
+    }
+  }
+  if (st == DPX_OK) {
+    int max_lanes = 1;
+    for (const auto& d : p->designs) max_lanes = std::max(max_lanes, d.lanes);
+    if (hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_offset, hipEventDisableTiming) != hipSuccess) {
+      st = fail(DPX_E_DEVICE, "event creation failed");
+    }
+    for (int l = 1; l < max_lanes && st == DPX_OK; ++l) {
+      hipStream_t q = nullptr;
+      hipEvent_t e = nullptr;
+      // default priority, non-blocking with respect to the legacy default stream
+      if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        st = fail(DPX_E_DEVICE, "stream creation failed");
+        break;
+      }
+      p->aux.push_back(q);
+      p->ev_join.push_back(e);
     }
   }
   if (st == DPX_OK && o.autotune && o.force_variant < 0) {
@@ -566,6 +638,10 @@ dpx_status dpx_plan_destroy(dpx_plan* p) {
   }
   for (auto& d : p->designs) free_design(d);
   for (auto& kv : p->twiddles) hipFree(kv.second);
+  for (auto q : p->aux) (void)hipStreamDestroy(q);
+  for (auto e : p->ev_join) (void)hipEventDestroy(e);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_offset) (void)hipEventDestroy(p->ev_offset);
   delete p;
   return ok();
 }
@@ -610,14 +686,23 @@ dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* in
   hipStream_t s = static_cast<hipStream_t>(stream);
   p->fwd_valid = false;
   for (const auto& d : p->designs) {
-    for (int w0 = 0; w0 < d.W; w0 += d.wl_chunk) {
+    DPX_TRY(fork_lanes(p, d, s));
+    for (int c = 0; c < d.nchunks; ++c) {
+      const int lane = c % d.lanes;
+      const int w0 = c * d.wl_chunk;
       const int wc = std::min(d.wl_chunk, d.W - w0);
-      DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, s));
-      const float2* of = (p->opts.checkpoint_mode == 1) ? d.ofov : d.ofov + static_cast<int64_t>(w0) * d.F * d.F;
+      hipStream_t ls = lane_stream(p, lane, s);
+      if (lane == 1 && c == 1) DPX_HIP(hipStreamWaitEvent(ls, p->ev_offset, 0));
+      DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, lane, ls,
+                            (c == 0 && d.lanes > 1) ? p->ev_offset : nullptr));
+      const float2* of = (p->opts.checkpoint_mode == 1)
+                             ? d.ofov + static_cast<int64_t>(lane) * d.wl_chunk * d.F * d.F
+                             : d.ofov + static_cast<int64_t>(w0) * d.F * d.F;
       hipError_t e = dpx::launch_bin_intensity(of, intensity + d.img_off + static_cast<int64_t>(w0) * d.T * d.T,
-                                               wc, d.F, d.b, s);
+                                               wc, d.F, d.b, ls);
       if (e != hipSuccess) return fail(DPX_E_DEVICE, "intensity launch failed: %s", hipGetErrorString(e));
     }
+    DPX_TRY(join_lanes(p, d, s));
   }
   p->fwd_valid = (p->opts.checkpoint_mode == 0);
   p->last_h = h;
@@ -659,13 +744,21 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
                 "u_in");
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (const auto& d : p->designs) {
-    int chunk_i = 0;
-    for (int w0 = 0; w0 < d.W; w0 += d.wl_chunk, ++chunk_i) {
+    DPX_TRY(fork_lanes(p, d, s));
+    for (int c = 0; c < d.nchunks; ++c) {
+      const int lane = c % d.lanes;
+      const int w0 = c * d.wl_chunk;
       const int wc = std::min(d.wl_chunk, d.W - w0);
-      if (!store) DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, s));
-      DPX_TRY(adjoint_chunk(p, d, h, dl_di, w0, wc, chunk_i > 0, s));
+      hipStream_t ls = lane_stream(p, lane, s);
+      if (lane == 1 && c == 1) DPX_HIP(hipStreamWaitEvent(ls, p->ev_offset, 0));
+      hipEvent_t first_ev = (c == 0 && d.lanes > 1) ? p->ev_offset : nullptr;
+      if (!store) {
+        DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, lane, ls, first_ev));
+        first_ev = nullptr;
+      }
+      DPX_TRY(adjoint_chunk(p, d, h, dl_di, w0, wc, lane, c >= d.lanes, ls, first_ev));
     }
-    (void)chunk_i;
+    DPX_TRY(join_lanes(p, d, s));
     const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;
     hipError_t e = dpx::launch_dh_reduce(d.dh_part, dl_dh + d.h_off, d.nslots, per, s);
     if (e != hipSuccess) return fail(DPX_E_DEVICE, "gradient reduction launch failed: %s", hipGetErrorString(e));

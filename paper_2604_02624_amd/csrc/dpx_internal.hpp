@@ -80,5 +80,6 @@ bool fft_size_supported(int M);
 // host: per-stage twiddle table of the length-M transform (layout in fft.hpp)
 void build_twiddle_table(int M, std::vector<float2>& out);
 int row_lanes_per_transform(int M);  // P = M / E
+int row_rows_per_block(int M, int mode);  // rows (transforms) per row-pass block
 
 }  // namespace dpx

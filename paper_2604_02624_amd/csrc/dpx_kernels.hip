@@ -29,14 +29,19 @@ __device__ __forceinline__ float2 transmission(float h, const WlConst& c) {
   return t;
 }
 
-constexpr int kRowThreads = 256;
+// Threads per row-pass block: 512 (eight transforms of 1024) where the registers allow two
+// such blocks per CU next to their LDS, 256 for the register-heavy adjoint middle pass.
+constexpr int row_threads_of_mode(int mode) { return mode == ROW_ADJ_MID ? 256 : 512; }
+template <int M, int MODE>
+constexpr int row_block_threads() { return row_threads_of_mode(MODE); }
 
 // ------------------------------------------------------------------------------------------
 // Row pass.  A block owns G = 256 / P consecutive rows (one transform group per row) and
 // loops over a run of wavelengths, so the row's heights stay in registers.
 // ------------------------------------------------------------------------------------------
 template <int M, int PAD, int MODE>
-__global__ void __launch_bounds__(kRowThreads) row_kernel(RowArgs a) {
+__global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs a) {
+  constexpr int kRowThreads = row_block_threads<M, MODE>();
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
   constexpr int G = kRowThreads / P;
@@ -412,12 +417,15 @@ __global__ void fill_zero_kernel(float* p, int64_t n) {
 template <int M, int PAD>
 static hipError_t row_dispatch_mode(int mode, const RowArgs& a, dim3 grid, hipStream_t s) {
   switch (mode) {
-    case ROW_FWD_FIRST: row_kernel<M, PAD, ROW_FWD_FIRST><<<grid, kRowThreads, 0, s>>>(a); break;
-    case ROW_FWD_MID: row_kernel<M, PAD, ROW_FWD_MID><<<grid, kRowThreads, 0, s>>>(a); break;
-    case ROW_FWD_LAST: row_kernel<M, PAD, ROW_FWD_LAST><<<grid, kRowThreads, 0, s>>>(a); break;
-    case ROW_ADJ_SEED: row_kernel<M, PAD, ROW_ADJ_SEED><<<grid, kRowThreads, 0, s>>>(a); break;
-    case ROW_ADJ_MID: row_kernel<M, PAD, ROW_ADJ_MID><<<grid, kRowThreads, 0, s>>>(a); break;
-    case ROW_ADJ_LAST: row_kernel<M, PAD, ROW_ADJ_LAST><<<grid, kRowThreads, 0, s>>>(a); break;
+#define DPX_ROW(MD) \
+  case MD: row_kernel<M, PAD, MD><<<grid, row_block_threads<M, MD>(), 0, s>>>(a); break;
+    DPX_ROW(ROW_FWD_FIRST)
+    DPX_ROW(ROW_FWD_MID)
+    DPX_ROW(ROW_FWD_LAST)
+    DPX_ROW(ROW_ADJ_SEED)
+    DPX_ROW(ROW_ADJ_MID)
+    DPX_ROW(ROW_ADJ_LAST)
+#undef DPX_ROW
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -480,6 +488,12 @@ int row_lanes_per_transform(int M) {
     default:
       return 0;
   }
+}
+
+int row_rows_per_block(int M, int mode) {
+  const int P = row_lanes_per_transform(M);
+  if (P == 0) return 0;
+  return row_threads_of_mode(mode) / P;
 }
 
 hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,

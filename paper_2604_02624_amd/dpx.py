@@ -33,7 +33,8 @@ class COpts(ctypes.Structure):
     _fields_ = [("checkpoint_mode", ctypes.c_int32), ("wl_chunk", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("force_variant", ctypes.c_int32), ("check_finite", ctypes.c_int32),
-                ("max_workspace_bytes", ctypes.c_int64)]
+                ("max_workspace_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CLayout(ctypes.Structure):
@@ -123,13 +124,14 @@ def _c_designs(designs):
 
 
 def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
-          autotune=0):
+          autotune=0, streams=0):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
     o.wl_chunk = wl_chunk
     o.force_variant = force_variant
     o.autotune = int(autotune)
+    o.streams = int(streams)
     o.max_workspace_bytes = max_workspace_bytes
     return o
 
@@ -165,14 +167,16 @@ class Plan:
     device, packed over designs as the C ABI describes."""
 
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
-                 force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False):
+                 force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False,
+                 streams: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
         self.lib = load_library()
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
-        o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune)
+        o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune,
+                  streams)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))

@@ -59,9 +59,11 @@ def test_query_store_vs_recompute_memory(lib):
                        z=3e-5, fov=64)
     store = _query([d])
     rec = _query([d], checkpoint_mode=1, wl_chunk=64)
-    assert store > 48 * 2 ** 30            # 16 GiB spectra + 32 GiB checkpoints
+    assert store > 32 * 2 ** 30            # 32 GiB of checkpoints alone
     assert rec < 2 * 2 ** 30
     assert store < 288e9                    # fits one MI355X
+    one = _query([d], streams=1)            # single lane, whole-workload spectra: 16 GiB more
+    assert one - store >= 8 * 2 ** 30
 
 
 @pytest.mark.parametrize("field,value,status", [

@@ -288,6 +288,15 @@ def test_recompute_mode_and_column_variants_agree(torch_dev):
     rec = run_gpu(torch_dev, [d], [h], [tau], checkpoint_mode=1, wl_chunk=48)
     assert torch_dev.equal(rec["I"], base["I"])
     assert rel_l2(rec["dh"].cpu().numpy(), base["dh"].cpu().numpy()) <= 1e-6
+    for streams, chunk in ((1, 0), (2, 32), (3, 40)):
+        r = run_gpu(torch_dev, [d], [h], [tau], streams=streams, wl_chunk=chunk)
+        assert torch_dev.equal(r["I"], base["I"])
+        assert rel_l2(r["dh"].cpu().numpy(), base["dh"].cpu().numpy()) <= 1e-6
+        r2 = run_gpu(torch_dev, [d], [h], [tau], streams=streams, wl_chunk=chunk)
+        assert torch_dev.equal(r2["dh"], r["dh"])         # reproducible at a fixed lane layout
+    rc = run_gpu(torch_dev, [d], [h], [tau], checkpoint_mode=1, wl_chunk=32, streams=2)
+    assert torch_dev.equal(rc["I"], base["I"])
+    assert rel_l2(rc["dh"].cpu().numpy(), base["dh"].cpu().numpy()) <= 1e-6
     for v in range(len(dpx.variant_names())):
         r = run_gpu(torch_dev, [d], [h], [tau], force_variant=v)
         assert r["plan"].variant(0) == v
