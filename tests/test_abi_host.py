@@ -62,8 +62,8 @@ def test_query_store_vs_recompute_memory(lib):
     assert store > 32 * 2 ** 30            # 32 GiB of checkpoints alone
     assert rec < 2 * 2 ** 30
     assert store < 288e9                    # fits one MI355X
-    one = _query([d], streams=1)            # single lane, whole-workload spectra: 16 GiB more
-    assert one - store >= 8 * 2 ** 30
+    two = _query([d], streams=2)            # two lanes of quarter-size chunks: 8 GiB of spectra
+    assert store - two >= 8 * 2 ** 30       # instead of 16 GiB for the whole workload at once
 
 
 @pytest.mark.parametrize("field,value,status", [
