@@ -190,10 +190,11 @@ typedef enum dpx_pass {
 dpx_status dpx_timing_enable(dpx_plan* plan, int32_t enable);
 
 /* Waits for the recorded events and returns, for pass `pass`, the summed kernel time in
- * milliseconds, the number of launches and the summed algorithmic bytes since the timers
- * were enabled.  Any output pointer may be NULL. */
+ * milliseconds, the number of launches, the summed algorithmic bytes and the summed
+ * algorithmic floating-point operations (each length-M transform counted as 5 M log2 M, each
+ * complex product as 6) since the timers were enabled.  Any output pointer may be NULL. */
 dpx_status dpx_timing_read(dpx_plan* plan, int32_t pass, double* total_ms, int64_t* launches,
-                           int64_t* bytes);
+                           int64_t* bytes, double* flops);
 
 /* Message for the last failed call on this thread ("" if none).  Valid until the next call
  * on this thread. */

@@ -76,12 +76,14 @@ struct TimedLaunch {
   int pass;
   hipEvent_t start, stop;
   int64_t bytes;
+  double flops;
 };
 
 struct PassTotals {
   double ms = 0.0;
   int64_t launches = 0;
   int64_t bytes = 0;
+  double flops = 0.0;
 };
 
 struct dpx_plan {
@@ -301,6 +303,24 @@ dpx_status timer_end(dpx_plan* p, hipStream_t s, TimedLaunch& t) {
   return DPX_OK;
 }
 
+// conventional operation count of one complex transform of length m: 5 m log2 m
+double fft_flops(int m) { return 5.0 * m * std::log2(static_cast<double>(m)); }
+
+// algorithmic floating-point work of one launch: transforms at the conventional count plus
+// 6 flops per complex product (transmission, transfer function, gradient term)
+double row_flops(const Design& d, int mode, int wc, int rows) {
+  const double per_row_fft = fft_flops(d.M);
+  switch (mode) {
+    case dpx::ROW_FWD_FIRST: return static_cast<double>(wc) * rows * (per_row_fft + 6.0 * d.N);
+    case dpx::ROW_FWD_MID: return static_cast<double>(wc) * rows * (2 * per_row_fft + 6.0 * d.N);
+    case dpx::ROW_FWD_LAST: return static_cast<double>(wc) * rows * per_row_fft;
+    case dpx::ROW_ADJ_SEED: return static_cast<double>(wc) * rows * per_row_fft;
+    case dpx::ROW_ADJ_MID: return static_cast<double>(wc) * rows * (2 * per_row_fft + 12.0 * d.N);
+    case dpx::ROW_ADJ_LAST: return static_cast<double>(wc) * rows * (per_row_fft + 6.0 * d.N);
+    default: return 0.0;
+  }
+}
+
 // algorithmic bytes of one row-pass launch (every operand read or written once)
 int64_t row_bytes(const Design& d, int mode, int wc, int nwb, bool accumulate, bool has_u) {
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
@@ -325,7 +345,8 @@ dpx_status run_row(dpx_plan* p, const Design& d, int mode, RowArgs a, int row_lo
   const int nrb = (row_hi - row_lo + rg - 1) / rg;
   const int nwb = (a.w_count + d.w_per_block - 1) / d.w_per_block;
   TimedLaunch t{DPX_PASS_ROW_FWD_FIRST + mode, nullptr, nullptr,
-                row_bytes(d, mode, a.w_count, nwb, a.accumulate != 0, a.u_in != nullptr)};
+                row_bytes(d, mode, a.w_count, nwb, a.accumulate != 0, a.u_in != nullptr),
+                row_flops(d, mode, a.w_count, row_hi - row_lo)};
   DPX_TRY(timer_begin(p, s, t));
   hipError_t e = dpx::launch_row(d.M, d.pad, mode, a, nrb, nwb, s);
   if (e != hipSuccess) return fail(DPX_E_DEVICE, "row pass (mode %d) launch failed: %s", mode, hipGetErrorString(e));
@@ -347,7 +368,8 @@ dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj,
   c.out_hi = out_hi;
   c.w_begin = w0;
   TimedLaunch t{conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD, nullptr, nullptr,
-                static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo))};
+                static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo)),
+                static_cast<double>(wc) * d.M * (2 * fft_flops(d.M) + 6.0 * d.M)};
   DPX_TRY(timer_begin(p, s, t));
   hipError_t e = dpx::launch_col(d.M, d.pad, conj, d.col_variant, c, wc, s);
   if (e != hipSuccess) return fail(DPX_E_DEVICE, "column pass launch failed: %s", hipGetErrorString(e));
@@ -779,7 +801,8 @@ dpx_status dpx_timing_enable(dpx_plan* p, int32_t enable) {
   return ok();
 }
 
-dpx_status dpx_timing_read(dpx_plan* p, int32_t pass, double* total_ms, int64_t* launches, int64_t* bytes) {
+dpx_status dpx_timing_read(dpx_plan* p, int32_t pass, double* total_ms, int64_t* launches, int64_t* bytes,
+                           double* flops) {
   if (!p) return fail(DPX_E_ARG, "plan is NULL");
   if (pass < 0 || pass >= DPX_PASS_COUNT) return fail(DPX_E_ARG, "pass %d out of range", pass);
   for (auto& t : p->pending) {
@@ -790,6 +813,7 @@ dpx_status dpx_timing_read(dpx_plan* p, int32_t pass, double* total_ms, int64_t*
     a.ms += ms;
     a.launches += 1;
     a.bytes += t.bytes;
+    a.flops += t.flops;
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
   }
@@ -798,6 +822,7 @@ dpx_status dpx_timing_read(dpx_plan* p, int32_t pass, double* total_ms, int64_t*
   if (total_ms) *total_ms = a.ms;
   if (launches) *launches = a.launches;
   if (bytes) *bytes = a.bytes;
+  if (flops) *flops = a.flops;
   return ok();
 }
 

@@ -86,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.dpx_plan_variant.restype = ctypes.c_int
     lib.dpx_timing_enable.argtypes = [vp, i32]
     lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
-                                    ctypes.POINTER(i64)]
+                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     lib.dpx_timing_enable.restype = ctypes.c_int
     lib.dpx_timing_read.restype = ctypes.c_int
     lib.dpx_last_error.argtypes = []
@@ -278,10 +278,10 @@ class Plan:
     def timing_read(self) -> dict:
         out = {}
         for i, name in enumerate(self.PASS_NAMES):
-            ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+            ms, n, b, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
             _check(self.lib, self.lib.dpx_timing_read(self._h, i, ctypes.byref(ms), ctypes.byref(n),
-                                                      ctypes.byref(b)))
-            out[name] = dict(ms=ms.value, launches=n.value, bytes=b.value)
+                                                      ctypes.byref(b), ctypes.byref(f)))
+            out[name] = dict(ms=ms.value, launches=n.value, bytes=b.value, flops=f.value)
         return out
 
     @staticmethod
