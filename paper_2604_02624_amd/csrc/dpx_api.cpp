@@ -367,6 +367,11 @@ dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj,
   c.out_lo = out_lo;
   c.out_hi = out_hi;
   c.w_begin = w0;
+  c.w_count = wc;
+  // two wavelengths per column block (the second one's rows are prefetched while the first
+  // is transformed; measured best of 1, 2, 4, 8 on the large workload) when that still
+  // leaves several blocks per CU
+  c.col_wpb = (static_cast<int64_t>(wc) * (d.M / 8) >= 2 * 8192) ? 2 : 1;
   TimedLaunch t{conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD, nullptr, nullptr,
                 static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo)),
                 static_cast<double>(wc) * d.M * (2 * fft_flops(d.M) + 6.0 * d.M)};

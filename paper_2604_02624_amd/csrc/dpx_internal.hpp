@@ -56,7 +56,9 @@ struct ColArgs {
   int n;
   int in_lo, in_hi;          // rows holding non-zero input (others read as zero)
   int out_lo, out_hi;        // rows whose output is kept
-  int w_begin;               // global wavelength of blockIdx.y == 0
+  int w_begin;               // global wavelength of chunk-local wavelength 0
+  int w_count;               // wavelengths in this launch
+  int col_wpb;               // wavelengths each block runs (>= 1)
 };
 
 // launchers (dpx_kernels.hip); each returns a hipError_t from the launch

@@ -237,6 +237,7 @@ col_kernel(ColArgs a) {
   constexpr int LD = Geo<M>::COL_REGION;  // one column's staging rows / exchange region
   constexpr int EN = E / PAD;
   constexpr bool HALF = (PAD == 2);
+  static_assert(NT / TX == P, "staging rows per pass");
   __shared__ float2 tile[TX * LD];
   __shared__ float2 tw[twiddle_count<M>()];
 
@@ -250,67 +251,88 @@ col_kernel(ColArgs a) {
     tile_x = (tile_x & ~15) + ((r & 7) << 1) + (r >> 3);
   }
   const int kx0 = tile_x * TX;
-  float2* spec = a.spec + static_cast<size_t>(blockIdx.y) * N * M;
-  const WlConst c = a.wl[a.w_begin + blockIdx.y];
-
   const int cc = threadIdx.x % TX;
   const int yy = threadIdx.x / TX;
-  for (int y = a.in_lo + yy; y < a.in_hi; y += NT / TX)
-    tile[cc * LD + y] = spec[static_cast<size_t>(y) * M + kx0 + cc];
-  stage_twiddles<M>(tw, a.tw, threadIdx.x, NT);
-  __syncthreads();
-
   const int g = threadIdx.x / P;
   const int j0 = threadIdx.x % P;
   float2* lds = tile + g * LD;
-  float2 reg[E];
-#pragma unroll
-  for (int t = 0; t < EN; ++t) {
-    const int y = j0 + P * t;
-    reg[t] = (y >= a.in_lo && y < a.in_hi) ? lds[y] : make_float2(0.f, 0.f);
-  }
-  wave_sync();
-  fft<M, false, HALF>(reg, lds, j0, tw);
-
-  // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0.
   const int kx = kx0 + g;
   const int kxs = kx < M / 2 ? kx : kx - M;
-  const double base = c.q0 - static_cast<double>(kxs * kxs);
-  if constexpr (MIRROR) {
-    // H depends on ky^2 only: lane j0 holds ky = j0 + P t, and for t >= E/2 the row M - ky
-    // is register E-1-t of lane P - j0 (lane 0 mirrors onto its own register E - t), so
-    // each lane evaluates E/2 + 1 rows and fetches the others across lanes.
-    // Streamed so that only two evaluations are live at a time: step u applies row u and the
-    // mirrored row E-1-u (whose value lane 0 takes from its own evaluation u+1).
-    constexpr int EH = E / 2;
-    const int lane = threadIdx.x & 63;
-    const int src = ((lane - j0) + ((P - j0) & (P - 1))) << 2;
-    float2 cur = transfer<M, CONJ>(a.zrev, base, j0);
+
+  // The block runs a.col_wpb wavelengths; the staged rows of the next one are loaded into
+  // registers while the current one is transformed, so their latency is hidden.
+  const int wb = blockIdx.y * a.col_wpb;
+  const int we = min(wb + a.col_wpb, a.w_count);
+  float2 pre[EN];
+  auto fetch = [&](int w) {
+    const float2* sp = a.spec + static_cast<size_t>(w) * N * M + kx0 + cc;
 #pragma unroll
-    for (int u = 0; u < EH; ++u) {
-      const float2 nxt = transfer<M, CONJ>(a.zrev, base, j0 + P * (u + 1));
-      reg[u] = cmul(reg[u], cur);
-      float2 m;
-      m.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.x)));
-      m.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.y)));
-      if (j0 == 0) m = nxt;
-      reg[E - 1 - u] = cmul(reg[E - 1 - u], m);
-      cur = nxt;
+    for (int k = 0; k < EN; ++k) {
+      const int y = a.in_lo + yy + k * P;
+      pre[k] = (y < a.in_hi) ? sp[static_cast<size_t>(y) * M] : make_float2(0.f, 0.f);
     }
-  } else {
+  };
+  fetch(wb);
+  stage_twiddles<M>(tw, a.tw, threadIdx.x, NT);
+
+  for (int w = wb; w < we; ++w) {
 #pragma unroll
-    for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], transfer<M, CONJ>(a.zrev, base, j0 + P * t));
-  }
-  fft<M, true, false>(reg, lds, j0, tw);
-  wave_sync();
+    for (int k = 0; k < EN; ++k) {
+      const int y = a.in_lo + yy + k * P;
+      if (y < a.in_hi) tile[cc * LD + y] = pre[k];
+    }
+    __syncthreads();
+    if (w + 1 < we) fetch(w + 1);
+
+    const WlConst c = a.wl[a.w_begin + w];
+    float2 reg[E];
 #pragma unroll
-  for (int t = 0; t < EN; ++t) {
-    const int y = j0 + P * t;
-    if (y >= a.out_lo && y < a.out_hi) lds[y] = reg[t];
+    for (int t = 0; t < EN; ++t) {
+      const int y = j0 + P * t;
+      reg[t] = (y >= a.in_lo && y < a.in_hi) ? lds[y] : make_float2(0.f, 0.f);
+    }
+    wave_sync();
+    fft<M, false, HALF>(reg, lds, j0, tw);
+
+    // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0.
+    const double base = c.q0 - static_cast<double>(kxs * kxs);
+    if constexpr (MIRROR) {
+      // H depends on ky^2 only: lane j0 holds ky = j0 + P t, and for t >= E/2 the row M - ky
+      // is register E-1-t of lane P - j0 (lane 0 mirrors onto its own register E - t), so
+      // each lane evaluates E/2 + 1 rows and fetches the others across lanes.  Streamed so
+      // that only two evaluations are live at a time: step u applies row u and the mirrored
+      // row E-1-u (whose value lane 0 takes from its own evaluation u+1).
+      constexpr int EH = E / 2;
+      const int lane = threadIdx.x & 63;
+      const int src = ((lane - j0) + ((P - j0) & (P - 1))) << 2;
+      float2 cur = transfer<M, CONJ>(a.zrev, base, j0);
+#pragma unroll
+      for (int u = 0; u < EH; ++u) {
+        const float2 nxt = transfer<M, CONJ>(a.zrev, base, j0 + P * (u + 1));
+        reg[u] = cmul(reg[u], cur);
+        float2 m;
+        m.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.x)));
+        m.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.y)));
+        if (j0 == 0) m = nxt;
+        reg[E - 1 - u] = cmul(reg[E - 1 - u], m);
+        cur = nxt;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], transfer<M, CONJ>(a.zrev, base, j0 + P * t));
+    }
+    fft<M, true, false>(reg, lds, j0, tw);
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < EN; ++t) {
+      const int y = j0 + P * t;
+      if (y >= a.out_lo && y < a.out_hi) lds[y] = reg[t];
+    }
+    __syncthreads();
+    float2* sp = a.spec + static_cast<size_t>(w) * N * M + kx0 + cc;
+    for (int y = a.out_lo + yy; y < a.out_hi; y += P) sp[static_cast<size_t>(y) * M] = tile[cc * LD + y];
+    __syncthreads();  // the next wavelength's staging overwrites the tile
   }
-  __syncthreads();
-  for (int y = a.out_lo + yy; y < a.out_hi; y += NT / TX)
-    spec[static_cast<size_t>(y) * M + kx0 + cc] = tile[cc * LD + y];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -521,7 +543,7 @@ int default_col_variant(int M) { return M >= 512 ? 2 : 3; }
 
 template <int M, int PAD, int TX, bool MIRROR>
 static hipError_t col_launch(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
-  dim3 grid(M / TX, w_count);
+  dim3 grid(M / TX, (w_count + a.col_wpb - 1) / a.col_wpb);
   if (conj)
     col_kernel<M, PAD, true, TX, MIRROR><<<grid, TX * Geo<M>::P, 0, s>>>(a);
   else
