@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--checkpoint-mode", type=int, default=0, choices=[0, 1])
     ap.add_argument("--wl-chunk", type=int, default=0)
     ap.add_argument("--streams", type=int, default=0, help="concurrent chunk lanes (0 automatic)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay HIP graphs of each call (per-pass timers then come from one extra "
+                         "direct step after the timed region)")
     ap.add_argument("--variant", type=int, default=-1, help="column-pass variant (-1 automatic)")
     ap.add_argument("--autotune", action="store_true", help="time column-pass variants at plan creation")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -162,7 +165,8 @@ def main():
     w = wk.make_workload(args.workload)
     designs = w["designs"]
     plan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
-                    force_variant=args.variant, autotune=args.autotune, streams=args.streams)
+                    force_variant=args.variant, autotune=args.autotune, streams=args.streams,
+                    use_graph=args.graph)
     variant = dpx.variant_names()[plan.variant(0)]
     log(f"[bench] column-pass variant {variant}")
     h = plan.pack_heights(w["h"])
@@ -192,7 +196,8 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup step {i + 1}/{args.warmup} done")
 
-    plan.timing(True)
+    if not args.graph:
+        plan.timing(True)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -204,7 +209,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"[bench] {args.steps} timed steps done in {wall:.3f} s")
-    passes = plan.timing_read()
+    if args.graph:
+        plan.timing(True)
+        step()
+        torch.cuda.synchronize()
+        passes = plan.timing_read()
+        passes = {k: dict(v, ms=v["ms"] * args.steps, bytes=v["bytes"] * args.steps,
+                          flops=v["flops"] * args.steps, launches=v["launches"] * args.steps)
+                  for k, v in passes.items()}
+    else:
+        passes = plan.timing_read()
     plan.timing(False)
     ms_step = ev0.elapsed_time(ev1) / args.steps
     value = props / (ms_step / 1e3)
@@ -263,7 +277,8 @@ def main():
         config=dict(workload=WORKLOAD_NAMES[args.workload], designs=len(designs),
                     wavelengths=sum(d["n_wl"] for d in designs), layers=d0["layers"], n=d0["n"],
                     transform=d0["n"] * d0["pad"], checkpoint_mode=args.checkpoint_mode,
-                    wl_chunk=args.wl_chunk, streams=args.streams, column_variant=variant,
+                    wl_chunk=args.wl_chunk, streams=args.streams, graph=args.graph,
+                    column_variant=variant,
                     phase_args="f64"),
         roofline=roofline, cpu_baseline=cpu, plain_loop=plain,
         vs_plain_loop=(round(value / plain["value"], 2) if plain else None),

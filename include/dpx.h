@@ -92,7 +92,12 @@ typedef struct dpx_opts {
                                (K*W*N*N complex per design) for the backward;
                                1: backward recomputes the forward chunk by chunk */
   int32_t wl_chunk;         /* wavelengths per chunk (0 = automatic) */
-  int32_t use_graph;        /* reserved: capture launch sequences in HIP graphs */
+  int32_t use_graph;        /* nonzero: the first dpx_forward / dpx_loss / dpx_backward with a
+                               given set of buffer pointers captures its launches into a HIP
+                               graph, later calls with the same pointers replay it (on a
+                               plan-owned stream ordered after and before the caller's stream
+                               by events).  Buffer contents may change between calls; the
+                               pointers may not.  Per-pass timers run the launches directly. */
   int32_t autotune;         /* nonzero: dpx_plan_create times every column-pass variant on
                                each distinct transform length and keeps the fastest */
   int32_t force_variant;    /* -1: automatic (autotuned if asked, else a built-in choice per

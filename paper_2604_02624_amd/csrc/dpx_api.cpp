@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -91,6 +92,12 @@ struct dpx_plan {
   std::vector<hipStream_t> aux;   // lanes 1..L-1 (lane 0 is the caller's stream)
   hipEvent_t ev_fork = nullptr, ev_offset = nullptr;
   std::vector<hipEvent_t> ev_join;
+  // HIP-graph replay (opts.use_graph): one executable graph per call kind and pointer set,
+  // replayed on a plan-owned stream joined to the caller's stream by events
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_gin = nullptr, ev_gout = nullptr;
+  std::map<std::array<uintptr_t, 5>, hipGraphExec_t> graphs;
+  std::vector<std::array<uintptr_t, 5>> graph_order;
   bool timing = false;
   std::vector<TimedLaunch> pending;
   PassTotals totals[DPX_PASS_COUNT];
@@ -493,6 +500,54 @@ dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
   return DPX_OK;
 }
 
+constexpr size_t kMaxGraphs = 16;
+
+// Runs `enqueue` on the caller's stream, or (opts.use_graph, timers off) replays a graph of
+// it captured on the first call with the same key.
+template <typename F>
+dpx_status run_graph_or_eager(dpx_plan* p, const std::array<uintptr_t, 5>& key, hipStream_t s,
+                              F&& enqueue) {
+  if (!p->opts.use_graph || p->timing) return enqueue(s);
+  DPX_HIP(hipEventRecord(p->ev_gin, s));
+  DPX_HIP(hipStreamWaitEvent(p->gstream, p->ev_gin, 0));
+  auto it = p->graphs.find(key);
+  if (it == p->graphs.end()) {
+    if (p->graphs.size() >= kMaxGraphs) {
+      auto old = p->graphs.find(p->graph_order.front());
+      if (old != p->graphs.end()) {
+        (void)hipGraphExecDestroy(old->second);
+        p->graphs.erase(old);
+      }
+      p->graph_order.erase(p->graph_order.begin());
+    }
+    DPX_HIP(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeRelaxed));
+    const dpx_status st = enqueue(p->gstream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->gstream, &g);
+    if (st != DPX_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(DPX_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(DPX_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    it = p->graphs.emplace(key, ex).first;
+    p->graph_order.push_back(key);
+  }
+  DPX_HIP(hipGraphLaunch(it->second, p->gstream));
+  DPX_HIP(hipEventRecord(p->ev_gout, p->gstream));
+  DPX_HIP(hipStreamWaitEvent(s, p->ev_gout, 0));
+  return DPX_OK;
+}
+
+template <typename... T>
+std::array<uintptr_t, 5> graph_key(uintptr_t kind, T... ptrs) {
+  std::array<uintptr_t, 5> k{kind, reinterpret_cast<uintptr_t>(ptrs)...};
+  return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -641,6 +696,12 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
       p->ev_join.push_back(e);
     }
   }
+  if (st == DPX_OK && o.use_graph) {
+    if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_gin, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_gout, hipEventDisableTiming) != hipSuccess)
+      st = fail(DPX_E_DEVICE, "graph stream creation failed");
+  }
   if (st == DPX_OK && o.autotune && o.force_variant < 0) {
     std::map<int, int> cache;
     for (auto& d : p->designs)
@@ -665,6 +726,10 @@ dpx_status dpx_plan_destroy(dpx_plan* p) {
   }
   for (auto& d : p->designs) free_design(d);
   for (auto& kv : p->twiddles) hipFree(kv.second);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->gstream) (void)hipStreamDestroy(p->gstream);
+  if (p->ev_gin) (void)hipEventDestroy(p->ev_gin);
+  if (p->ev_gout) (void)hipEventDestroy(p->ev_gout);
   for (auto q : p->aux) (void)hipStreamDestroy(q);
   for (auto e : p->ev_join) (void)hipEventDestroy(e);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
@@ -710,27 +775,31 @@ dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* in
   DPX_TRY(check_ptr(intensity, 4, "intensity"));
   if (u_in) DPX_TRY(check_ptr(u_in, 8, "u_in"));
   DPX_TRY(sticky_check());
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStream_t caller = static_cast<hipStream_t>(stream);
   p->fwd_valid = false;
-  for (const auto& d : p->designs) {
-    DPX_TRY(fork_lanes(p, d, s));
-    for (int c = 0; c < d.nchunks; ++c) {
-      const int lane = c % d.lanes;
-      const int w0 = c * d.wl_chunk;
-      const int wc = std::min(d.wl_chunk, d.W - w0);
-      hipStream_t ls = lane_stream(p, lane, s);
-      if (lane == 1 && c == 1) DPX_HIP(hipStreamWaitEvent(ls, p->ev_offset, 0));
-      DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, lane, ls,
-                            (c == 0 && d.lanes > 1) ? p->ev_offset : nullptr));
-      const float2* of = (p->opts.checkpoint_mode == 1)
-                             ? d.ofov + static_cast<int64_t>(lane) * d.wl_chunk * d.F * d.F
-                             : d.ofov + static_cast<int64_t>(w0) * d.F * d.F;
-      hipError_t e = dpx::launch_bin_intensity(of, intensity + d.img_off + static_cast<int64_t>(w0) * d.T * d.T,
-                                               wc, d.F, d.b, ls);
-      if (e != hipSuccess) return fail(DPX_E_DEVICE, "intensity launch failed: %s", hipGetErrorString(e));
+  auto enqueue = [&](hipStream_t s) -> dpx_status {
+    for (const auto& d : p->designs) {
+      DPX_TRY(fork_lanes(p, d, s));
+      for (int c = 0; c < d.nchunks; ++c) {
+        const int lane = c % d.lanes;
+        const int w0 = c * d.wl_chunk;
+        const int wc = std::min(d.wl_chunk, d.W - w0);
+        hipStream_t ls = lane_stream(p, lane, s);
+        if (lane == 1 && c == 1) DPX_HIP(hipStreamWaitEvent(ls, p->ev_offset, 0));
+        DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, lane, ls,
+                              (c == 0 && d.lanes > 1) ? p->ev_offset : nullptr));
+        const float2* of = (p->opts.checkpoint_mode == 1)
+                               ? d.ofov + static_cast<int64_t>(lane) * d.wl_chunk * d.F * d.F
+                               : d.ofov + static_cast<int64_t>(w0) * d.F * d.F;
+        hipError_t e = dpx::launch_bin_intensity(
+            of, intensity + d.img_off + static_cast<int64_t>(w0) * d.T * d.T, wc, d.F, d.b, ls);
+        if (e != hipSuccess) return fail(DPX_E_DEVICE, "intensity launch failed: %s", hipGetErrorString(e));
+      }
+      DPX_TRY(join_lanes(p, d, s));
     }
-    DPX_TRY(join_lanes(p, d, s));
-  }
+    return DPX_OK;
+  };
+  DPX_TRY(run_graph_or_eager(p, graph_key(1, h, u_in, intensity, nullptr), caller, enqueue));
   p->fwd_valid = (p->opts.checkpoint_mode == 0);
   p->last_h = h;
   p->last_u = u_in;
@@ -745,14 +814,18 @@ dpx_status dpx_loss(dpx_plan* p, const float* intensity, const float* target, do
   DPX_TRY(check_ptr(loss, 8, "loss"));
   if (dl_di) DPX_TRY(check_ptr(dl_di, 4, "dl_di"));
   DPX_TRY(sticky_check());
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (size_t i = 0; i < p->designs.size(); ++i) {
-    const Design& d = p->designs[i];
-    hipError_t e = dpx::launch_loss(intensity + d.img_off, target + d.img_off, dl_di ? dl_di + d.img_off : nullptr,
-                                    d.per_wl, d.W, d.T, s);
-    if (e == hipSuccess) e = dpx::launch_loss_sum(d.per_wl, loss + i, d.W, s);
-    if (e != hipSuccess) return fail(DPX_E_DEVICE, "loss launch failed: %s", hipGetErrorString(e));
-  }
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  auto enqueue = [&](hipStream_t s) -> dpx_status {
+    for (size_t i = 0; i < p->designs.size(); ++i) {
+      const Design& d = p->designs[i];
+      hipError_t e = dpx::launch_loss(intensity + d.img_off, target + d.img_off,
+                                      dl_di ? dl_di + d.img_off : nullptr, d.per_wl, d.W, d.T, s);
+      if (e == hipSuccess) e = dpx::launch_loss_sum(d.per_wl, loss + i, d.W, s);
+      if (e != hipSuccess) return fail(DPX_E_DEVICE, "loss launch failed: %s", hipGetErrorString(e));
+    }
+    return DPX_OK;
+  };
+  DPX_TRY(run_graph_or_eager(p, graph_key(2, intensity, target, loss, dl_di), caller, enqueue));
   return ok();
 }
 
@@ -769,27 +842,31 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
     return fail(DPX_E_STATE,
                 "store-mode backward needs a preceding dpx_forward on this plan with the same h and "
                 "u_in");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (const auto& d : p->designs) {
-    DPX_TRY(fork_lanes(p, d, s));
-    for (int c = 0; c < d.nchunks; ++c) {
-      const int lane = c % d.lanes;
-      const int w0 = c * d.wl_chunk;
-      const int wc = std::min(d.wl_chunk, d.W - w0);
-      hipStream_t ls = lane_stream(p, lane, s);
-      if (lane == 1 && c == 1) DPX_HIP(hipStreamWaitEvent(ls, p->ev_offset, 0));
-      hipEvent_t first_ev = (c == 0 && d.lanes > 1) ? p->ev_offset : nullptr;
-      if (!store) {
-        DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, lane, ls, first_ev));
-        first_ev = nullptr;
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  auto enqueue = [&](hipStream_t s) -> dpx_status {
+    for (const auto& d : p->designs) {
+      DPX_TRY(fork_lanes(p, d, s));
+      for (int c = 0; c < d.nchunks; ++c) {
+        const int lane = c % d.lanes;
+        const int w0 = c * d.wl_chunk;
+        const int wc = std::min(d.wl_chunk, d.W - w0);
+        hipStream_t ls = lane_stream(p, lane, s);
+        if (lane == 1 && c == 1) DPX_HIP(hipStreamWaitEvent(ls, p->ev_offset, 0));
+        hipEvent_t first_ev = (c == 0 && d.lanes > 1) ? p->ev_offset : nullptr;
+        if (!store) {
+          DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, lane, ls, first_ev));
+          first_ev = nullptr;
+        }
+        DPX_TRY(adjoint_chunk(p, d, h, dl_di, w0, wc, lane, c >= d.lanes, ls, first_ev));
       }
-      DPX_TRY(adjoint_chunk(p, d, h, dl_di, w0, wc, lane, c >= d.lanes, ls, first_ev));
+      DPX_TRY(join_lanes(p, d, s));
+      const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;
+      hipError_t e = dpx::launch_dh_reduce(d.dh_part, dl_dh + d.h_off, d.nslots, per, s);
+      if (e != hipSuccess) return fail(DPX_E_DEVICE, "gradient reduction launch failed: %s", hipGetErrorString(e));
     }
-    DPX_TRY(join_lanes(p, d, s));
-    const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;
-    hipError_t e = dpx::launch_dh_reduce(d.dh_part, dl_dh + d.h_off, d.nslots, per, s);
-    if (e != hipSuccess) return fail(DPX_E_DEVICE, "gradient reduction launch failed: %s", hipGetErrorString(e));
-  }
+    return DPX_OK;
+  };
+  DPX_TRY(run_graph_or_eager(p, graph_key(3, h, u_in, dl_di, dl_dh), caller, enqueue));
   return ok();
 }
 

@@ -124,7 +124,7 @@ def _c_designs(designs):
 
 
 def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
-          autotune=0, streams=0):
+          autotune=0, streams=0, use_graph=0):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
@@ -132,6 +132,7 @@ def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_by
     o.force_variant = force_variant
     o.autotune = int(autotune)
     o.streams = int(streams)
+    o.use_graph = int(use_graph)
     o.max_workspace_bytes = max_workspace_bytes
     return o
 
@@ -168,7 +169,7 @@ class Plan:
 
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
                  force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False,
-                 streams: int = 0):
+                 streams: int = 0, use_graph: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
@@ -176,7 +177,7 @@ class Plan:
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
         o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune,
-                  streams)
+                  streams, use_graph)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))

@@ -324,6 +324,37 @@ def test_variants_agree_on_every_transform_length(torch_dev):
             assert torch_dev.equal(r["dh"], outs[0]["dh"])
 
 
+def test_graph_replay_matches_direct_launches(torch_dev):
+    say("HIP-graph replay vs direct launches, several replays with direct work between")
+    from paper_2604_02624_amd import dpx
+    w = wk.make_workload(5)
+    ds, hs, taus = w["designs"][:6], w["h"][:6], w["targets"][:6]
+    ref = run_gpu(torch_dev, ds, hs, taus)
+    plan = dpx.Plan(ds, use_graph=True)
+    h = plan.pack_heights(hs)
+    tau = plan.pack_images(taus)
+    I = torch_dev.empty(plan.img_count, device="cuda")
+    g = torch_dev.empty(plan.img_count, device="cuda")
+    L = torch_dev.empty(len(ds), dtype=torch_dev.float64, device="cuda")
+    dh = torch_dev.empty(plan.h_count, device="cuda")
+    for rep in range(4):
+        if rep == 2:
+            h.mul_(1.0)          # direct work between replays
+        plan.forward(h, None, I)
+        plan.loss(I, tau, L, g)
+        plan.backward(h, None, g, dh)
+        torch_dev.cuda.synchronize()
+        assert torch_dev.equal(I, ref["I"]), rep
+        assert torch_dev.equal(dh, ref["dh"]), rep
+    # new contents at the same pointers are picked up by the replay
+    h2 = plan.pack_heights([x * 0.5 for x in hs])
+    h.copy_(h2)
+    plan.forward(h, None, I)
+    torch_dev.cuda.synchronize()
+    ref2 = run_gpu(torch_dev, ds, [x * 0.5 for x in hs], taus, backward=False)
+    assert torch_dev.equal(I, ref2["I"])
+
+
 def test_error_paths(torch_dev):
     say("error paths")
     from paper_2604_02624_amd import dpx
