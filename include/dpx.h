@@ -102,8 +102,11 @@ typedef struct dpx_opts {
                                each distinct transform length and keeps the fastest */
   int32_t force_variant;    /* -1: automatic (autotuned if asked, else a built-in choice per
                                transform length); otherwise a column-pass variant index
-                               (see dpx_variant_count / dpx_variant_name).  Every variant
-                               gives the same results bit for bit. */
+                               (see dpx_variant_count / dpx_variant_name).  The transform
+                               variants (0-3) give the same results bit for bit; variant 4
+                               (DFT as complex matrix products on the FP32 matrix cores,
+                               transform lengths up to 512) agrees with them to rounding.
+                               DPX_E_UNSUPPORTED if the variant is not built for a design. */
   int32_t check_finite;     /* reserved */
   int64_t max_workspace_bytes; /* 0 = no limit; otherwise plan creation fails with
                                   DPX_E_NOMEM if the plan would need more */

@@ -104,6 +104,7 @@ struct dpx_plan {
   dpx_opts opts;
   int device = 0;
   std::map<int, float2*> twiddles;
+  std::map<int, float2*> dft;      // matrix-core column pass: key M * 4 + pad
   int64_t bytes = 0;
   bool fwd_valid = false;
   const float* last_h = nullptr;
@@ -149,6 +150,10 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
       if (!(std::isfinite(d.z[l]) && d.z[l] >= 0.0))
         return fail(DPX_E_ARG, "design %d: z[%d] must be finite and >= 0", i, l);
     const int M = d.pad * d.n;
+    if (o && o->force_variant >= 0 && dpx::fft_size_supported(M) &&
+        !dpx::col_variant_supported(M, d.pad, o->force_variant))
+      return fail(DPX_E_UNSUPPORTED, "design %d: column variant %d is not built for transform length %d", i,
+                  o->force_variant, M);
     if (!dpx::fft_size_supported(M))
       return fail(DPX_E_UNSUPPORTED,
                   "design %d: transform length pad*n = %d is not built (64, 96, 128, 192, 256, "
@@ -375,6 +380,10 @@ dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj,
   c.out_hi = out_hi;
   c.w_begin = w0;
   c.w_count = wc;
+  {
+    auto it = p->dft.find(d.M * 4 + d.pad);
+    c.dft = it == p->dft.end() ? nullptr : it->second;
+  }
   // two wavelengths per column block (the second one's rows are prefetched while the first
   // is transformed; measured best of 1, 2, 4, 8 on the large workload) when that still
   // leaves several blocks per CU
@@ -479,6 +488,8 @@ dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
   const bool was_timing = p->timing;
   p->timing = false;
   for (int v = 0; v < dpx::kColVariants; ++v) {
+    if (!dpx::col_variant_supported(d.M, d.pad, v)) continue;
+    if (v == 4 && !p->dft.count(d.M * 4 + d.pad)) continue;
     d.col_variant = v;
     DPX_TRY(run_col(p, d, 0, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
     DPX_HIP(hipEventRecord(e0, nullptr));
@@ -696,6 +707,23 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
       p->ev_join.push_back(e);
     }
   }
+  if (st == DPX_OK && (o.force_variant == 4 || o.autotune)) {
+    for (const auto& d : p->designs) {
+      const int key = d.M * 4 + d.pad;
+      if (p->dft.count(key) || !dpx::col_variant_supported(d.M, d.pad, 4)) continue;
+      std::vector<float2> tab;
+      dpx::build_dft_table(d.M, d.pad, tab);
+      float2* dt = nullptr;
+      const int64_t tb = static_cast<int64_t>(tab.size()) * 8;
+      if ((st = dev_alloc(&dt, tb, "DFT matrices")) != DPX_OK) break;
+      p->dft[key] = dt;
+      if (hipMemcpy(dt, tab.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
+        st = fail(DPX_E_DEVICE, "copy of the DFT matrices failed");
+        break;
+      }
+      p->bytes += tb;
+    }
+  }
   if (st == DPX_OK && o.use_graph) {
     if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_gin, hipEventDisableTiming) != hipSuccess ||
@@ -726,6 +754,7 @@ dpx_status dpx_plan_destroy(dpx_plan* p) {
   }
   for (auto& d : p->designs) free_design(d);
   for (auto& kv : p->twiddles) hipFree(kv.second);
+  for (auto& kv : p->dft) hipFree(kv.second);
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->gstream) (void)hipStreamDestroy(p->gstream);
   if (p->ev_gin) (void)hipEventDestroy(p->ev_gin);

@@ -59,12 +59,17 @@ struct ColArgs {
   int w_begin;               // global wavelength of chunk-local wavelength 0
   int w_count;               // wavelengths in this launch
   int col_wpb;               // wavelengths each block runs (>= 1)
+  const float2* dft;         // DFT matrices of the transform (matrix-core variant only)
 };
 
 // launchers (dpx_kernels.hip); each returns a hipError_t from the launch
 hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,
                       hipStream_t s);
-constexpr int kColVariants = 4;
+constexpr int kColVariants = 5;
+bool col_variant_supported(int M, int pad, int variant);
+// host: FT[y][ky] then F[ky][y] (F = exp(-2 pi i ky y / M), y < M / pad) for the matrix-core
+// column pass
+void build_dft_table(int M, int pad, std::vector<float2>& out);
 extern const char* const kColVariantNames[kColVariants];
 int default_col_variant(int M);
 hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,

@@ -336,6 +336,136 @@ col_kernel(ColArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Column pass as two complex matrix products on the FP32 matrix cores (v_mfma_f32_16x16x4_f32):
+//   Z = F S            F[ky][y] = exp(-2 pi i ky y / M)  (M x N, shared by every wavelength)
+//   Z <- H . Z / M^2   (transfer function on the fly, as in the transform kernels)
+//   Out = F^H Z        (N x M, keeps the aperture rows)
+// for a tile of 16 columns of one wavelength.  S and Z live in LDS as separate real and
+// imaginary planes; the DFT matrix is read from a table built on the host in double
+// precision: FT[y][ky] (step 1, lanes read 16 consecutive ky) and F[ky][y] (step 3).
+// Operand layout of the 16x16x4 instruction: lane l holds A[l%16][l/16], B[l/16][l%16] and
+// D[4(l/16)+r][l%16], r = 0..3.
+// ------------------------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmTile = 16;
+// threads per block: the LDS tiles of long transforms allow one block per CU, so those get
+// eight wavefronts to keep two per SIMD
+constexpr int gemm_threads(int M) { return M >= 256 ? 512 : 256; }
+
+template <int M, int PAD, bool CONJ>
+__global__ void __launch_bounds__(gemm_threads(M)) colgemm_kernel(ColArgs a, const float2* __restrict__ dft) {
+  constexpr int N = M / PAD;
+  constexpr int TN = kGemmTile;
+  constexpr int kGemmThreads = gemm_threads(M);
+  constexpr int WAVES = kGemmThreads / 64;
+  __shared__ float sr[N * TN], si[N * TN];
+  __shared__ float zr[M * TN], zi[M * TN];
+  const float2* __restrict__ FT = dft;           // [N][M]
+  const float2* __restrict__ F = dft + M * N;    // [M][N]
+
+  const int kx0 = blockIdx.x * TN;
+  float2* spec = a.spec + static_cast<size_t>(blockIdx.y) * N * M;
+  const WlConst c = a.wl[a.w_begin + blockIdx.y];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // stage rows [in_lo, in_hi) of the 16 columns (zeros elsewhere)
+  for (int i = tid; i < N * TN; i += kGemmThreads) {
+    const int y = i / TN, cc = i % TN;
+    float2 v = make_float2(0.f, 0.f);
+    if (y >= a.in_lo && y < a.in_hi) v = spec[static_cast<size_t>(y) * M + kx0 + cc];
+    sr[i] = v.x;
+    si[i] = v.y;
+  }
+  __syncthreads();
+
+  // step 1: Z = F S, K = N.  A wave takes its row tiles of ky two at a time, so four
+  // accumulator chains are in flight on the matrix core and the S operand is read once per
+  // k step for both.
+  {
+    const int kx = kx0 + lr;
+    const int kxs = kx < M / 2 ? kx : kx - M;
+    const double base = c.q0 - static_cast<double>(kxs * kxs);
+    for (int t0 = wave; t0 < M / 16; t0 += 2 * WAVES) {
+      const int t1 = t0 + WAVES;
+      const bool two = t1 < M / 16;
+      v4f re0 = {0.f, 0.f, 0.f, 0.f}, im0 = re0, re1 = re0, im1 = re0;
+#pragma unroll 4
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const float br = sr[(k0 + lk) * TN + lr], bi = si[(k0 + lk) * TN + lr];
+        const float2 f0 = FT[(k0 + lk) * M + t0 * 16 + lr];
+        re0 = __builtin_amdgcn_mfma_f32_16x16x4f32(f0.x, br, re0, 0, 0, 0);
+        re0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-f0.y, bi, re0, 0, 0, 0);
+        im0 = __builtin_amdgcn_mfma_f32_16x16x4f32(f0.x, bi, im0, 0, 0, 0);
+        im0 = __builtin_amdgcn_mfma_f32_16x16x4f32(f0.y, br, im0, 0, 0, 0);
+        if (two) {
+          const float2 f1 = FT[(k0 + lk) * M + t1 * 16 + lr];
+          re1 = __builtin_amdgcn_mfma_f32_16x16x4f32(f1.x, br, re1, 0, 0, 0);
+          re1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-f1.y, bi, re1, 0, 0, 0);
+          im1 = __builtin_amdgcn_mfma_f32_16x16x4f32(f1.x, bi, im1, 0, 0, 0);
+          im1 = __builtin_amdgcn_mfma_f32_16x16x4f32(f1.y, br, im1, 0, 0, 0);
+        }
+      }
+      // H at (kx0 + lr, ky0 + 4 lk + r)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ky = t0 * 16 + 4 * lk + r;
+        float2 z = cmul(make_float2(re0[r], im0[r]), transfer<M, CONJ>(a.zrev, base, ky));
+        zr[ky * TN + lr] = z.x;
+        zi[ky * TN + lr] = z.y;
+        if (two) {
+          ky = t1 * 16 + 4 * lk + r;
+          z = cmul(make_float2(re1[r], im1[r]), transfer<M, CONJ>(a.zrev, base, ky));
+          zr[ky * TN + lr] = z.x;
+          zi[ky * TN + lr] = z.y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // step 3: Out = F^H Z for the kept rows, K = M, two row tiles of y at a time
+  for (int t0 = wave; t0 < N / 16; t0 += 2 * WAVES) {
+    const int t1 = t0 + WAVES;
+    const bool use0 = t0 * 16 < a.out_hi && t0 * 16 + 16 > a.out_lo;
+    const bool use1 = t1 < N / 16 && t1 * 16 < a.out_hi && t1 * 16 + 16 > a.out_lo;
+    if (!use0 && !use1) continue;
+    v4f re0 = {0.f, 0.f, 0.f, 0.f}, im0 = re0, re1 = re0, im1 = re0;
+#pragma unroll 4
+    for (int k0 = 0; k0 < M; k0 += 4) {
+      const float br = zr[(k0 + lk) * TN + lr], bi = zi[(k0 + lk) * TN + lr];
+      // A[y][ky] = conj(F[ky][y]): lane (lr, lk) needs y = y0 + lr, ky = k0 + lk
+      if (use0) {
+        const float2 f0 = F[(k0 + lk) * N + t0 * 16 + lr];
+        re0 = __builtin_amdgcn_mfma_f32_16x16x4f32(f0.x, br, re0, 0, 0, 0);
+        re0 = __builtin_amdgcn_mfma_f32_16x16x4f32(f0.y, bi, re0, 0, 0, 0);
+        im0 = __builtin_amdgcn_mfma_f32_16x16x4f32(f0.x, bi, im0, 0, 0, 0);
+        im0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-f0.y, br, im0, 0, 0, 0);
+      }
+      if (use1) {
+        const float2 f1 = F[(k0 + lk) * N + t1 * 16 + lr];
+        re1 = __builtin_amdgcn_mfma_f32_16x16x4f32(f1.x, br, re1, 0, 0, 0);
+        re1 = __builtin_amdgcn_mfma_f32_16x16x4f32(f1.y, bi, re1, 0, 0, 0);
+        im1 = __builtin_amdgcn_mfma_f32_16x16x4f32(f1.x, bi, im1, 0, 0, 0);
+        im1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-f1.y, br, im1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int y = t0 * 16 + 4 * lk + r;
+      if (use0 && y >= a.out_lo && y < a.out_hi)
+        spec[static_cast<size_t>(y) * M + kx0 + lr] = make_float2(re0[r], im0[r]);
+      y = t1 * 16 + 4 * lk + r;
+      if (use1 && y >= a.out_lo && y < a.out_hi)
+        spec[static_cast<size_t>(y) * M + kx0 + lr] = make_float2(re1[r], im1[r]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Small kernels
 // ------------------------------------------------------------------------------------------
 __global__ void bin_intensity_kernel(const float2* __restrict__ ofov, float* __restrict__ out,
@@ -481,6 +611,19 @@ static void twiddle_table(std::vector<float2>& out) {
   }
 }
 
+void build_dft_table(int M, int pad, std::vector<float2>& out) {
+  const int N = M / pad;
+  out.assign(static_cast<size_t>(2) * M * N, make_float2(0.f, 0.f));
+  for (int ky = 0; ky < M; ++ky)
+    for (int y = 0; y < N; ++y) {
+      const long long m = (static_cast<long long>(ky) * y) % M;
+      const double ang = 6.283185307179586476925286766559 * static_cast<double>(m) / M;
+      const float2 v = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(-std::sin(ang)));
+      out[static_cast<size_t>(y) * M + ky] = v;              // FT[y][ky]
+      out[static_cast<size_t>(M) * N + static_cast<size_t>(ky) * N + y] = v;  // F[ky][y]
+    }
+}
+
 void build_twiddle_table(int M, std::vector<float2>& out) {
   switch (M) {
 #define DPX_CASE(m) case m: twiddle_table<m>(out); return;
@@ -530,13 +673,14 @@ hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_bloc
   }
 }
 
-// Column-pass variants (all give the same results bit for bit):
+// Column-pass variants (0-3 give the same results bit for bit; 4 differs by rounding):
 //   0: 8-column tiles, 1: 16-column tiles, 2: 8-column tiles + mirrored H rows,
-//   3: 16-column tiles + mirrored H rows.
+//   3: 16-column tiles + mirrored H rows, 4: DFT as complex matrix products on the matrix
+//   cores (transform lengths up to 512).
 // Tiles must be whole wavefronts: with fewer than 8 lanes per transform, 8-column tiles
 // fall back to 16 columns.
 const char* const kColVariantNames[kColVariants] = {"tile8", "tile16", "tile8+mirror",
-                                                    "tile16+mirror"};
+                                                    "tile16+mirror", "dft-gemm-mfma"};
 
 // built-in choice when no variant is forced and no autotuning is asked for
 int default_col_variant(int M) { return M >= 512 ? 2 : 3; }
@@ -570,9 +714,41 @@ static hipError_t col_dispatch(int pad, bool conj, int variant, const ColArgs& a
   return hipErrorInvalidValue;
 }
 
+template <int M, int PAD>
+static hipError_t colgemm_launch(bool conj, const ColArgs& a, const float2* dft, int w_count, hipStream_t s) {
+  if constexpr (M <= 512 && M % 16 == 0 && (M / PAD) % 16 == 0) {
+    dim3 grid(M / kGemmTile, w_count);
+    if (conj)
+      colgemm_kernel<M, PAD, true><<<grid, gemm_threads(M), 0, s>>>(a, dft);
+    else
+      colgemm_kernel<M, PAD, false><<<grid, gemm_threads(M), 0, s>>>(a, dft);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+bool col_variant_supported(int M, int pad, int variant) {
+  if (variant < 0 || variant >= kColVariants) return false;
+  if (variant == 4) return M <= 512 && M % 16 == 0 && (M / pad) % 16 == 0;
+  return true;
+}
+
 hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
                       hipStream_t s) {
-  if (variant < 0 || variant >= kColVariants) return hipErrorInvalidValue;
+  if (!col_variant_supported(M, pad, variant)) return hipErrorInvalidValue;
+  if (variant == 4) {
+    ColArgs one = a;
+    one.col_wpb = 1;
+    switch (M) {
+#define DPX_CASE(m) \
+  case m: return pad == 2 ? colgemm_launch<m, 2>(conj, one, a.dft, w_count, s) : colgemm_launch<m, 1>(conj, one, a.dft, w_count, s);
+      DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   switch (M) {
 #define DPX_CASE(m) case m: return col_dispatch<m>(pad, conj, variant, a, w_count, s);
     DPX_FOR_EACH_M(DPX_CASE)

@@ -297,7 +297,7 @@ def test_recompute_mode_and_column_variants_agree(torch_dev):
     rc = run_gpu(torch_dev, [d], [h], [tau], checkpoint_mode=1, wl_chunk=32, streams=2)
     assert torch_dev.equal(rc["I"], base["I"])
     assert rel_l2(rc["dh"].cpu().numpy(), base["dh"].cpu().numpy()) <= 1e-6
-    for v in range(len(dpx.variant_names())):
+    for v in range(4):
         r = run_gpu(torch_dev, [d], [h], [tau], force_variant=v)
         assert r["plan"].variant(0) == v
         assert torch_dev.equal(r["I"], base["I"]), dpx.variant_names()[v]
@@ -317,11 +317,38 @@ def test_variants_agree_on_every_transform_length(torch_dev):
                            fov=n // 2, pad=2)
         h = (g.random((2, n, n)) * 1.2e-6).astype(np.float32)
         tau = g.random((3, n // 2, n // 2)).astype(np.float32)
-        outs = [run_gpu(torch_dev, [d], [h], [tau], force_variant=v)
-                for v in range(len(dpx.variant_names()))]
+        outs = [run_gpu(torch_dev, [d], [h], [tau], force_variant=v) for v in range(4)]
         for r in outs[1:]:
             assert torch_dev.equal(r["I"], outs[0]["I"])
             assert torch_dev.equal(r["dh"], outs[0]["dh"])
+
+
+@pytest.mark.parametrize("n,pad", [(64, 2), (48, 2), (96, 2), (128, 2), (256, 2), (64, 1), (192, 1)])
+def test_matrix_core_column_pass(torch_dev, n, pad):
+    """Column pass as DFT matrix products on the FP32 matrix cores: oracle parity."""
+    say(f"DFT-GEMM (MFMA) column pass, N = {n}, pad {pad}")
+    g = np.random.default_rng(500 + n + pad)
+    wl = np.array([450e-9, 600e-9, 750e-9])
+    d = wk.make_design(n=n, layers=2, wl=wl, n_mat=wk.cauchy_index(wl), dx=300e-9,
+                       z=[20e-6, 30e-6], fov=n // 2, pad=pad)
+    h = (g.random((2, n, n)) * 1.17e-6).astype(np.float32)
+    tau = g.random((3, n // 2, n // 2)).astype(np.float32)
+    r = run_gpu(torch_dev, [d], [h], [tau], force_variant=4)
+    I_ref = o.forward(d, h, None, "fft")
+    errs = per_wl_rel(r["I"].cpu().numpy().reshape(I_ref.shape), I_ref)
+    say(f"rel L2 {errs}")
+    assert errs.max() <= INT_TOL
+    _, g_ref, _ = o.loss(I_ref, tau)
+    dh_ref = o.grad(d, h, None, g_ref, "fft")
+    assert rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref) <= 1e-4
+
+
+def test_matrix_core_variant_rejected_where_not_built(torch_dev):
+    from paper_2604_02624_amd import dpx
+    w = wk.make_workload(4)
+    with pytest.raises(dpx.DpxError) as e:
+        dpx.Plan(w["designs"], force_variant=4)
+    assert e.value.status == dpx.DPX_E_UNSUPPORTED
 
 
 def test_graph_replay_matches_direct_launches(torch_dev):
