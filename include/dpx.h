@@ -112,6 +112,9 @@ typedef struct dpx_opts {
                                   DPX_E_NOMEM if the plan would need more */
   int32_t streams;          /* wavelength chunks processed concurrently on this many streams
                                (the caller's plus streams the plan owns); 0 = automatic (1).
+                               Several designs in one plan run side by side on up to 4
+                               streams (or `streams`, if > 1); 1 keeps everything on the
+                               caller's stream.
                                The dL/dh summation order follows the lane layout, so results
                                agree to rounding across settings and bit for bit per setting. */
   int32_t reserved;

@@ -92,6 +92,10 @@ struct dpx_plan {
   std::vector<hipStream_t> aux;   // lanes 1..L-1 (lane 0 is the caller's stream)
   hipEvent_t ev_fork = nullptr, ev_offset = nullptr;
   std::vector<hipEvent_t> ev_join;
+  // independent designs spread over `dstreams` streams (the caller's plus aux[0..]);
+  // design i runs on stream design_stream[i]
+  int dstreams = 1;
+  std::vector<int> design_stream;
   // HIP-graph replay (opts.use_graph): one executable graph per call kind and pointer set,
   // replayed on a plan-owned stream joined to the caller's stream by events
   hipStream_t gstream = nullptr;
@@ -511,6 +515,27 @@ dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
   return DPX_OK;
 }
 
+// Runs fn(design, stream) for every design: on the caller's stream, or with several
+// independent designs spread over the plan's streams (forked from and joined back to s).
+template <typename F>
+dpx_status for_each_design(dpx_plan* p, hipStream_t s, F&& fn) {
+  if (p->dstreams <= 1) {
+    for (size_t i = 0; i < p->designs.size(); ++i) DPX_TRY(fn(p->designs[i], static_cast<int>(i), s));
+    return DPX_OK;
+  }
+  DPX_HIP(hipEventRecord(p->ev_fork, s));
+  for (int k = 1; k < p->dstreams; ++k) DPX_HIP(hipStreamWaitEvent(p->aux[k - 1], p->ev_fork, 0));
+  for (size_t i = 0; i < p->designs.size(); ++i) {
+    const int k = p->design_stream[i];
+    DPX_TRY(fn(p->designs[i], static_cast<int>(i), k == 0 ? s : p->aux[k - 1]));
+  }
+  for (int k = 1; k < p->dstreams; ++k) {
+    DPX_HIP(hipEventRecord(p->ev_join[k - 1], p->aux[k - 1]));
+    DPX_HIP(hipStreamWaitEvent(s, p->ev_join[k - 1], 0));
+  }
+  return DPX_OK;
+}
+
 constexpr size_t kMaxGraphs = 16;
 
 // Runs `enqueue` on the caller's stream, or (opts.use_graph, timers off) replays a graph of
@@ -690,6 +715,26 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
   if (st == DPX_OK) {
     int max_lanes = 1;
     for (const auto& d : p->designs) max_lanes = std::max(max_lanes, d.lanes);
+    // several independent designs (each on one lane) run side by side on up to four streams,
+    // assigned longest-first to the least loaded stream by their W K M N cost
+    if (nd > 1 && max_lanes == 1 && o.streams != 1) {
+      p->dstreams = std::min(nd, o.streams > 1 ? o.streams : 4);
+      std::vector<int> order(nd);
+      for (int i = 0; i < nd; ++i) order[i] = i;
+      auto cost = [&](int i) {
+        const Design& d = p->designs[i];
+        return static_cast<double>(d.W) * d.K * d.M * d.N;
+      };
+      std::sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+      std::vector<double> load(p->dstreams, 0.0);
+      p->design_stream.assign(nd, 0);
+      for (int i : order) {
+        const int k = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+        p->design_stream[i] = k;
+        load[k] += cost(i);
+      }
+      max_lanes = std::max(max_lanes, p->dstreams);
+    }
     if (hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_offset, hipEventDisableTiming) != hipSuccess) {
       st = fail(DPX_E_DEVICE, "event creation failed");
@@ -806,8 +851,8 @@ dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* in
   DPX_TRY(sticky_check());
   hipStream_t caller = static_cast<hipStream_t>(stream);
   p->fwd_valid = false;
-  auto enqueue = [&](hipStream_t s) -> dpx_status {
-    for (const auto& d : p->designs) {
+  auto enqueue = [&](hipStream_t s0) -> dpx_status {
+    return for_each_design(p, s0, [&](const Design& d, int, hipStream_t s) -> dpx_status {
       DPX_TRY(fork_lanes(p, d, s));
       for (int c = 0; c < d.nchunks; ++c) {
         const int lane = c % d.lanes;
@@ -824,9 +869,8 @@ dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* in
             of, intensity + d.img_off + static_cast<int64_t>(w0) * d.T * d.T, wc, d.F, d.b, ls);
         if (e != hipSuccess) return fail(DPX_E_DEVICE, "intensity launch failed: %s", hipGetErrorString(e));
       }
-      DPX_TRY(join_lanes(p, d, s));
-    }
-    return DPX_OK;
+      return join_lanes(p, d, s);
+    });
   };
   DPX_TRY(run_graph_or_eager(p, graph_key(1, h, u_in, intensity, nullptr), caller, enqueue));
   p->fwd_valid = (p->opts.checkpoint_mode == 0);
@@ -844,15 +888,14 @@ dpx_status dpx_loss(dpx_plan* p, const float* intensity, const float* target, do
   if (dl_di) DPX_TRY(check_ptr(dl_di, 4, "dl_di"));
   DPX_TRY(sticky_check());
   hipStream_t caller = static_cast<hipStream_t>(stream);
-  auto enqueue = [&](hipStream_t s) -> dpx_status {
-    for (size_t i = 0; i < p->designs.size(); ++i) {
-      const Design& d = p->designs[i];
+  auto enqueue = [&](hipStream_t s0) -> dpx_status {
+    return for_each_design(p, s0, [&](const Design& d, int i, hipStream_t s) -> dpx_status {
       hipError_t e = dpx::launch_loss(intensity + d.img_off, target + d.img_off,
                                       dl_di ? dl_di + d.img_off : nullptr, d.per_wl, d.W, d.T, s);
       if (e == hipSuccess) e = dpx::launch_loss_sum(d.per_wl, loss + i, d.W, s);
       if (e != hipSuccess) return fail(DPX_E_DEVICE, "loss launch failed: %s", hipGetErrorString(e));
-    }
-    return DPX_OK;
+      return DPX_OK;
+    });
   };
   DPX_TRY(run_graph_or_eager(p, graph_key(2, intensity, target, loss, dl_di), caller, enqueue));
   return ok();
@@ -872,8 +915,8 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
                 "store-mode backward needs a preceding dpx_forward on this plan with the same h and "
                 "u_in");
   hipStream_t caller = static_cast<hipStream_t>(stream);
-  auto enqueue = [&](hipStream_t s) -> dpx_status {
-    for (const auto& d : p->designs) {
+  auto enqueue = [&](hipStream_t s0) -> dpx_status {
+    return for_each_design(p, s0, [&](const Design& d, int, hipStream_t s) -> dpx_status {
       DPX_TRY(fork_lanes(p, d, s));
       for (int c = 0; c < d.nchunks; ++c) {
         const int lane = c % d.lanes;
@@ -892,8 +935,8 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
       const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;
       hipError_t e = dpx::launch_dh_reduce(d.dh_part, dl_dh + d.h_off, d.nslots, per, s);
       if (e != hipSuccess) return fail(DPX_E_DEVICE, "gradient reduction launch failed: %s", hipGetErrorString(e));
-    }
-    return DPX_OK;
+      return DPX_OK;
+    });
   };
   DPX_TRY(run_graph_or_eager(p, graph_key(3, h, u_in, dl_di, dl_dh), caller, enqueue));
   return ok();

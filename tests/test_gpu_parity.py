@@ -382,6 +382,19 @@ def test_graph_replay_matches_direct_launches(torch_dev):
     assert torch_dev.equal(I, ref2["I"])
 
 
+def test_concurrent_designs_match_sequential(torch_dev):
+    say("uneven designs on several streams vs one stream")
+    w = wk.make_workload(5)
+    ds, hs, taus = w["designs"][:12], w["h"][:12], w["targets"][:12]
+    seq = run_gpu(torch_dev, ds, hs, taus, streams=1)
+    par = run_gpu(torch_dev, ds, hs, taus)
+    par2 = run_gpu(torch_dev, ds, hs, taus, use_graph=True)
+    for r in (par, par2):
+        assert torch_dev.equal(r["I"], seq["I"])
+        assert torch_dev.equal(r["L"], seq["L"])
+        assert torch_dev.equal(r["dh"], seq["dh"])
+
+
 def test_error_paths(torch_dev):
     say("error paths")
     from paper_2604_02624_amd import dpx
