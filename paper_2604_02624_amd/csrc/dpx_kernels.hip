@@ -18,6 +18,15 @@
 namespace dpx {
 
 // Eq. 1 with the +j reading: t = exp(-ca h) exp(+i 2 pi rt h); phase argument in double.
+// Word 3 of a raw buffer resource on gfx9: 32-bit data format, no stride or swizzle.
+constexpr int kBufferRsrcWord3 = 0x00020000;
+
+// One 8-byte load through a buffer resource: byte offset = voff (per lane) + soff (scalar).
+__device__ __forceinline__ float2 buffer_load_c64(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+
 __device__ __forceinline__ float2 transmission(float h, const WlConst& c) {
   const double hd = static_cast<double>(h);
   float2 t = cis_turns(c.rt * hd);
@@ -259,30 +268,48 @@ col_kernel(ColArgs a) {
   const int kx = kx0 + g;
   const int kxs = kx < M / 2 ? kx : kx - M;
 
-  // The block runs a.col_wpb wavelengths; the staged rows of the next one are loaded into
-  // registers while the current one is transformed, so their latency is hidden.
+  // The block runs a.col_wpb wavelengths.  With zero padding the staged rows of the next one
+  // are loaded into registers while the current one is transformed, so their latency is
+  // hidden; without it those registers would not fit next to the full-length transform and
+  // the rows go straight to LDS.  Row k of a lane is one buffer load at the lane's 32-bit
+  // byte offset plus the scalar offset k P M 8, so no per-row address stays live.
+  constexpr bool PREFETCH = HALF;
   const int wb = blockIdx.y * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
-  float2 pre[EN];
+  const unsigned voff = static_cast<unsigned>(((a.in_lo + yy) * M + kx0 + cc) * 8);
+  auto plane = [&](int w) {
+    return __builtin_amdgcn_make_buffer_rsrc(a.spec + static_cast<size_t>(w) * N * M, 0,
+                                             N * M * 8, kBufferRsrcWord3);
+  };
+  float2 pre[PREFETCH ? EN : 1];
   auto fetch = [&](int w) {
-    const float2* sp = a.spec + static_cast<size_t>(w) * N * M + kx0 + cc;
+    const auto rs = plane(w);
 #pragma unroll
     for (int k = 0; k < EN; ++k) {
       const int y = a.in_lo + yy + k * P;
-      pre[k] = (y < a.in_hi) ? sp[static_cast<size_t>(y) * M] : make_float2(0.f, 0.f);
+      pre[PREFETCH ? k : 0] = (y < a.in_hi) ? buffer_load_c64(rs, voff, k * P * M * 8) : make_float2(0.f, 0.f);
+      if constexpr (!PREFETCH) {
+        if (y < a.in_hi) tile[cc * LD + y] = pre[0];
+      }
     }
   };
-  fetch(wb);
+  if constexpr (PREFETCH) fetch(wb);
   stage_twiddles<M>(tw, a.tw, threadIdx.x, NT);
 
   for (int w = wb; w < we; ++w) {
+    if constexpr (PREFETCH) {
 #pragma unroll
-    for (int k = 0; k < EN; ++k) {
-      const int y = a.in_lo + yy + k * P;
-      if (y < a.in_hi) tile[cc * LD + y] = pre[k];
+      for (int k = 0; k < EN; ++k) {
+        const int y = a.in_lo + yy + k * P;
+        if (y < a.in_hi) tile[cc * LD + y] = pre[k];
+      }
+    } else {
+      fetch(w);
     }
     __syncthreads();
-    if (w + 1 < we) fetch(w + 1);
+    if constexpr (PREFETCH) {
+      if (w + 1 < we) fetch(w + 1);
+    }
 
     const WlConst c = a.wl[a.w_begin + w];
     float2 reg[E];
