@@ -117,7 +117,20 @@ typedef struct dpx_opts {
                                caller's stream.
                                The dL/dh summation order follows the lane layout, so results
                                agree to rounding across settings and bit for bit per setting. */
-  int32_t reserved;
+  int32_t schedule;         /* how the passes of several designs are launched:
+                               0 = automatic (grouped when the plan holds several designs, no
+                               more than one stream is asked for and the grouped schedule
+                               applies; otherwise per design);
+                               1 = one launch per design and pass (designs on `streams`);
+                               2 = grouped: each pass of all designs that share a transform
+                               length, pad and mode is one launch (at most 64 designs per
+                               launch), in the order of the layers; the designs are split
+                               longest-first into up to 4 partitions (`streams` if > 1, one
+                               if `streams` is 1) whose launch lists run side by side on their
+                               own streams.  Needs checkpoint_mode 0,
+                               every design in one wavelength chunk on one stream and a
+                               transform column variant (0-3), else DPX_E_UNSUPPORTED.
+                               Results are bitwise identical across schedules. */
 } dpx_opts;
 
 /* Offsets (in elements of the buffer's type) of one design inside the packed buffers. */
@@ -217,6 +230,9 @@ const char* dpx_variant_name(int32_t v);
 
 /* The column-pass variant the plan uses for design `design`. */
 dpx_status dpx_plan_variant(const dpx_plan* plan, int32_t design, int32_t* variant);
+
+/* The schedule the plan runs: 1 = per design, 2 = grouped (see dpx_opts.schedule). */
+dpx_status dpx_plan_schedule(const dpx_plan* plan, int32_t* schedule);
 
 /* Library version string. */
 const char* dpx_version(void);

@@ -18,6 +18,9 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # no packed-FP32 instructions (v_pk_*_f32) anywhere in the device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # no implicit contraction: fused multiply-adds only where written (fmaf), so results
+          # do not depend on how a kernel inlines the shared code
+          "-ffp-contract=off",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 SOURCES = ["dpx_kernels.hip", "dpx_api.cpp"]
 

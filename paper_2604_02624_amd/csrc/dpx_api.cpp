@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <array>
 #include <map>
 #include <string>
@@ -87,6 +88,20 @@ struct PassTotals {
   double flops = 0.0;
 };
 
+// One launch of the grouped schedule.  g.tasks points into the plan's task buffer; g.call is
+// filled per call.
+enum GroupKind { GK_ROW, GK_COL, GK_BIN, GK_LOSS, GK_DH };
+struct GroupLaunch {
+  GroupKind kind;
+  int M = 0, pad = 0, mode = 0, variant = 0;
+  bool conj = false;
+  dpx::GroupArgs g{};
+  int pass = -1;           // DPX_PASS_* of row / column launches (timers)
+  int64_t bytes = 0;       // algorithmic bytes (without the input field)
+  int64_t u_bytes = 0;     // extra bytes when an input field is passed
+  double flops = 0.0;
+};
+
 struct dpx_plan {
   std::vector<Design> designs;
   std::vector<hipStream_t> aux;   // lanes 1..L-1 (lane 0 is the caller's stream)
@@ -109,6 +124,15 @@ struct dpx_plan {
   int device = 0;
   std::map<int, float2*> twiddles;
   std::map<int, float2*> dft;      // matrix-core column pass: key M * 4 + pad
+  // grouped schedule (opts.schedule): every pass of every design as one launch per transform
+  // length, mode and variant; task arrays in one device buffer
+  bool grouped = false;
+  // one forward / backward launch list per partition of the designs (partition k runs on
+  // stream k, as design_stream assigns); the loss is one list over all designs
+  std::vector<std::vector<GroupLaunch>> g_fwd, g_bwd;
+  std::vector<GroupLaunch> g_loss;
+  void* d_tasks = nullptr;
+  const dpx::LossTask* d_loss_tasks = nullptr;
   int64_t bytes = 0;
   bool fwd_valid = false;
   const float* last_h = nullptr;
@@ -127,6 +151,7 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
       return fail(DPX_E_ARG, "checkpoint_mode must be 0 or 1");
     if (o->wl_chunk < 0) return fail(DPX_E_ARG, "wl_chunk must be >= 0");
     if (o->streams < 0 || o->streams > 8) return fail(DPX_E_ARG, "streams must be in [0, 8]");
+    if (o->schedule < 0 || o->schedule > 2) return fail(DPX_E_ARG, "schedule must be 0, 1 or 2");
     if (o->max_workspace_bytes < 0) return fail(DPX_E_ARG, "max_workspace_bytes must be >= 0");
     if (o->force_variant < -1 || o->force_variant >= dpx::kColVariants)
       return fail(DPX_E_ARG, "force_variant must be -1 or a variant index below %d", dpx::kColVariants);
@@ -370,8 +395,8 @@ dpx_status run_row(dpx_plan* p, const Design& d, int mode, RowArgs a, int row_lo
   return DPX_OK;
 }
 
-dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj, int w0, int wc,
-                   int in_lo, int in_hi, int out_lo, int out_hi, hipStream_t s) {
+ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0, int wc, int in_lo,
+                 int in_hi, int out_lo, int out_hi) {
   ColArgs c{};
   c.spec = spec_of_lane(d, lane);
   c.wl = d.d_wl;
@@ -392,9 +417,22 @@ dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj,
   // is transformed; measured best of 1, 2, 4, 8 on the large workload) when that still
   // leaves several blocks per CU
   c.col_wpb = (static_cast<int64_t>(wc) * (d.M / 8) >= 2 * 8192) ? 2 : 1;
+  return c;
+}
+
+int64_t col_bytes(const Design& d, int wc, int in_lo, int in_hi, int out_lo, int out_hi) {
+  return static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo));
+}
+
+double col_flops(const Design& d, int wc) {
+  return static_cast<double>(wc) * d.M * (2 * fft_flops(d.M) + 6.0 * d.M);
+}
+
+dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj, int w0, int wc,
+                   int in_lo, int in_hi, int out_lo, int out_hi, hipStream_t s) {
+  const ColArgs c = col_args(p, d, lane, layer, w0, wc, in_lo, in_hi, out_lo, out_hi);
   TimedLaunch t{conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD, nullptr, nullptr,
-                static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo)),
-                static_cast<double>(wc) * d.M * (2 * fft_flops(d.M) + 6.0 * d.M)};
+                col_bytes(d, wc, in_lo, in_hi, out_lo, out_hi), col_flops(d, wc)};
   DPX_TRY(timer_begin(p, s, t));
   hipError_t e = dpx::launch_col(d.M, d.pad, conj, d.col_variant, c, wc, s);
   if (e != hipSuccess) return fail(DPX_E_DEVICE, "column pass launch failed: %s", hipGetErrorString(e));
@@ -448,6 +486,302 @@ dpx_status adjoint_chunk(dpx_plan* p, const Design& d, const float* h, const flo
     a.layer = l;
     a.h = h + h_off_layer(d, l);
     DPX_TRY(run_row(p, d, l > 0 ? dpx::ROW_ADJ_MID : dpx::ROW_ADJ_LAST, a, 0, d.N, s));
+  }
+  return DPX_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Grouped schedule.  Design i runs the passes FIRST, (column, MID)*, column, LAST forward and
+// SEED, (column, ADJ_MID)*, column, ADJ_LAST backward; position k of every design's sequence
+// becomes one launch per (transform length, pad, mode or variant), so the passes of all
+// designs share launches instead of queueing behind each other.
+// ------------------------------------------------------------------------------------------
+struct TaskBlob {
+  std::vector<char> bytes;
+  bool too_many_blocks = false;  // a launch would need more blocks than a grid can hold
+  size_t put(const void* src, size_t n) {
+    const size_t off = (bytes.size() + 255) / 256 * 256;
+    bytes.resize(off + n);
+    std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+};
+
+// Splits tasks into launches of at most kMaxGroupTasks; each task starts at a multiple of
+// `align` blocks.  g.tasks holds the blob offset until the blob is uploaded.
+template <typename Task>
+void add_group(std::vector<GroupLaunch>& out, const GroupLaunch& proto, const std::vector<Task>& tasks,
+               const std::vector<int>& nblocks, const std::vector<int>& align,
+               const std::vector<int64_t>& bytes, const std::vector<int64_t>& u_bytes,
+               const std::vector<double>& flops, TaskBlob& blob) {
+  for (size_t i0 = 0; i0 < tasks.size(); i0 += dpx::kMaxGroupTasks) {
+    const size_t n = std::min<size_t>(dpx::kMaxGroupTasks, tasks.size() - i0);
+    GroupLaunch L = proto;
+    L.g.ntasks = static_cast<int>(n);
+    int64_t b = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const int a = align[i0 + i];
+      b = (b + a - 1) / a * a;
+      L.g.block0[i] = static_cast<int>(b);
+      b += nblocks[i0 + i];
+      L.bytes += bytes[i0 + i];
+      L.u_bytes += u_bytes[i0 + i];
+      L.flops += flops[i0 + i];
+    }
+    if (b > std::numeric_limits<int>::max()) blob.too_many_blocks = true;
+    L.g.block0[n] = static_cast<int>(std::min<int64_t>(b, std::numeric_limits<int>::max()));
+    L.g.tasks = reinterpret_cast<const void*>(blob.put(tasks.data() + i0, n * sizeof(Task)));
+    out.push_back(L);
+  }
+}
+
+// Row launches of one position: designs (index, mode, layer, row range) grouped by key.
+struct RowItem {
+  int design, mode, layer, row_lo, row_hi;
+};
+
+void add_row_position(dpx_plan* p, const std::vector<RowItem>& items, std::vector<GroupLaunch>& out,
+                      TaskBlob& blob) {
+  std::map<std::array<int, 3>, std::vector<RowItem>> by_key;
+  for (const auto& it : items) {
+    const Design& d = p->designs[it.design];
+    by_key[{d.M, d.pad, it.mode}].push_back(it);
+  }
+  for (const auto& kv : by_key) {
+    std::vector<dpx::RowTask> tasks;
+    std::vector<int> nb, al;
+    std::vector<int64_t> by, ub;
+    std::vector<double> fl;
+    for (const auto& it : kv.second) {
+      const Design& d = p->designs[it.design];
+      dpx::RowTask t{};
+      t.a = row_args(p, d, 0, d.W, 0);
+      t.a.store_ckpt = (it.mode == dpx::ROW_FWD_FIRST || it.mode == dpx::ROW_FWD_MID) ? 1 : 0;
+      t.a.accumulate = 0;
+      t.a.layer = it.layer;
+      t.a.row_lo = it.row_lo;
+      t.a.row_hi = it.row_hi;
+      t.h_off = h_off_layer(d, it.layer);
+      t.u_off = d.u_off;
+      t.img_off = d.img_off;
+      const int rg = dpx::row_rows_per_block(d.M, it.mode);
+      t.gx = (it.row_hi - it.row_lo + rg - 1) / rg;
+      const int nwb = (d.W + d.w_per_block - 1) / d.w_per_block;
+      t.nblocks = t.gx * nwb;
+      tasks.push_back(t);
+      nb.push_back(t.nblocks);
+      al.push_back(1);
+      by.push_back(row_bytes(d, it.mode, d.W, nwb, false, false));
+      ub.push_back(it.mode == dpx::ROW_FWD_FIRST ? 8 * static_cast<int64_t>(d.N) * d.N : 0);
+      fl.push_back(row_flops(d, it.mode, d.W, it.row_hi - it.row_lo));
+    }
+    GroupLaunch proto{};
+    proto.kind = GK_ROW;
+    proto.M = kv.first[0];
+    proto.pad = kv.first[1];
+    proto.mode = kv.first[2];
+    proto.pass = DPX_PASS_ROW_FWD_FIRST + proto.mode;
+    add_group(out, proto, tasks, nb, al, by, ub, fl, blob);
+  }
+}
+
+// Column launches of one position: (design, layer, input rows, kept rows)
+struct ColItem {
+  int design, layer, in_lo, in_hi, out_lo, out_hi;
+};
+
+void add_col_position(dpx_plan* p, const std::vector<ColItem>& items, bool conj,
+                      std::vector<GroupLaunch>& out, TaskBlob& blob) {
+  std::map<std::array<int, 3>, std::vector<ColItem>> by_key;
+  for (const auto& it : items) {
+    const Design& d = p->designs[it.design];
+    by_key[{d.M, d.pad, d.col_variant}].push_back(it);
+  }
+  for (const auto& kv : by_key) {
+    std::vector<dpx::ColTask> tasks;
+    std::vector<int> nb, al;
+    std::vector<int64_t> by, ub;
+    std::vector<double> fl;
+    for (const auto& it : kv.second) {
+      const Design& d = p->designs[it.design];
+      dpx::ColTask t{};
+      t.a = col_args(p, d, 0, it.layer, 0, d.W, it.in_lo, it.in_hi, it.out_lo, it.out_hi);
+      t.gx = d.M / dpx::col_tile_width(d.M, d.col_variant);
+      t.nblocks = t.gx * ((d.W + t.a.col_wpb - 1) / t.a.col_wpb);
+      tasks.push_back(t);
+      nb.push_back(t.nblocks);
+      // column tiles pair up on an XCD in runs of 16 blocks counted from the task's start
+      al.push_back(t.gx % 16 == 0 ? 16 : 1);
+      by.push_back(col_bytes(d, d.W, it.in_lo, it.in_hi, it.out_lo, it.out_hi));
+      ub.push_back(0);
+      fl.push_back(col_flops(d, d.W));
+    }
+    GroupLaunch proto{};
+    proto.kind = GK_COL;
+    proto.M = kv.first[0];
+    proto.pad = kv.first[1];
+    proto.variant = kv.first[2];
+    proto.conj = conj;
+    proto.pass = conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD;
+    add_group(out, proto, tasks, nb, al, by, ub, fl, blob);
+  }
+}
+
+template <typename Task>
+void add_simple_group(std::vector<GroupLaunch>& out, GroupKind kind, const std::vector<Task>& tasks,
+                      const std::vector<int>& nblocks, TaskBlob& blob) {
+  GroupLaunch proto{};
+  proto.kind = kind;
+  const std::vector<int> al(tasks.size(), 1);
+  const std::vector<int64_t> z(tasks.size(), 0);
+  const std::vector<double> zf(tasks.size(), 0.0);
+  add_group(out, proto, tasks, nblocks, al, z, z, zf, blob);
+}
+
+// Whether every design can run in the grouped schedule: whole designs in one chunk on one
+// lane, stored checkpoints, a transform column variant.
+bool groupable(const dpx_plan* p) {
+  if (p->opts.checkpoint_mode != 0) return false;
+  for (const auto& d : p->designs)
+    if (d.nchunks != 1 || d.lanes != 1 || d.col_variant > 3) return false;
+  return true;
+}
+
+// forward and backward launch lists of the designs `ids`
+void build_group_lists(dpx_plan* p, const std::vector<int>& ids, std::vector<GroupLaunch>& fwd,
+                       std::vector<GroupLaunch>& bwd, TaskBlob& blob) {
+  int kmax = 0;
+  for (int i : ids) kmax = std::max(kmax, p->designs[i].K);
+  // forward
+  for (int j = 0; j <= kmax; ++j) {
+    std::vector<RowItem> rows;
+    for (int i : ids) {
+      const Design& d = p->designs[i];
+      if (j > d.K) continue;
+      const int fo = (d.N - d.F) / 2;
+      if (j == 0) rows.push_back({i, dpx::ROW_FWD_FIRST, 0, 0, d.N});
+      else if (j < d.K) rows.push_back({i, dpx::ROW_FWD_MID, j, 0, d.N});
+      else rows.push_back({i, dpx::ROW_FWD_LAST, 0, fo, fo + d.F});
+    }
+    add_row_position(p, rows, fwd, blob);
+    if (j == kmax) break;
+    std::vector<ColItem> cols;
+    for (int i : ids) {
+      const Design& d = p->designs[i];
+      if (j >= d.K) continue;
+      const int fo = (d.N - d.F) / 2;
+      const bool last = (j == d.K - 1);
+      cols.push_back({i, j, 0, d.N, last ? fo : 0, last ? fo + d.F : d.N});
+    }
+    add_col_position(p, cols, false, fwd, blob);
+  }
+  {
+    std::vector<dpx::BinTask> bins;
+    std::vector<int> nb;
+    for (int i : ids) {
+      const Design& d = p->designs[i];
+      bins.push_back({d.ofov, d.img_off, d.W, d.F, d.b});
+      nb.push_back(static_cast<int>((static_cast<int64_t>(d.W) * d.T * d.T + dpx::kGroupThreads - 1) /
+                                    dpx::kGroupThreads));
+    }
+    add_simple_group(fwd, GK_BIN, bins, nb, blob);
+  }
+  // backward
+  {
+    std::vector<RowItem> seeds;
+    for (int i : ids) {
+      const Design& d = p->designs[i];
+      const int fo = (d.N - d.F) / 2;
+      seeds.push_back({i, dpx::ROW_ADJ_SEED, 0, fo, fo + d.F});
+    }
+    add_row_position(p, seeds, bwd, blob);
+  }
+  for (int k = 0; k < kmax; ++k) {
+    std::vector<ColItem> cols;
+    std::vector<RowItem> rows;
+    for (int i : ids) {
+      const Design& d = p->designs[i];
+      if (k >= d.K) continue;
+      const int l = d.K - 1 - k;
+      const int fo = (d.N - d.F) / 2;
+      cols.push_back({i, l, k == 0 ? fo : 0, k == 0 ? fo + d.F : d.N, 0, d.N});
+      rows.push_back({i, l > 0 ? dpx::ROW_ADJ_MID : dpx::ROW_ADJ_LAST, l, 0, d.N});
+    }
+    add_col_position(p, cols, true, bwd, blob);
+    add_row_position(p, rows, bwd, blob);
+  }
+  {
+    std::vector<dpx::DhTask> dhs;
+    std::vector<int> nb;
+    for (int i : ids) {
+      const Design& d = p->designs[i];
+      const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;
+      dhs.push_back({d.dh_part, d.h_off, per, d.nslots});
+      nb.push_back(static_cast<int>((per + dpx::kGroupThreads - 1) / dpx::kGroupThreads));
+    }
+    add_simple_group(bwd, GK_DH, dhs, nb, blob);
+  }
+}
+
+dpx_status build_groups(dpx_plan* p) {
+  TaskBlob blob;
+  const int nd = static_cast<int>(p->designs.size());
+  const int parts = std::max(1, p->dstreams);
+  p->g_fwd.assign(parts, {});
+  p->g_bwd.assign(parts, {});
+  for (int k = 0; k < parts; ++k) {
+    std::vector<int> ids;
+    for (int i = 0; i < nd; ++i)
+      if ((p->design_stream.empty() ? 0 : p->design_stream[i]) == k) ids.push_back(i);
+    if (!ids.empty()) build_group_lists(p, ids, p->g_fwd[k], p->g_bwd[k], blob);
+  }
+  // loss: the task array in design order doubles as the table of the per-design sums
+  std::vector<dpx::LossTask> losses;
+  std::vector<int> lnb;
+  for (const auto& d : p->designs) {
+    losses.push_back({d.img_off, d.per_wl, d.W, d.T});
+    lnb.push_back(d.W);
+  }
+  add_simple_group(p->g_loss, GK_LOSS, losses, lnb, blob);
+  const size_t loss_table = blob.put(losses.data(), losses.size() * sizeof(dpx::LossTask));
+  if (blob.too_many_blocks)
+    return fail(DPX_E_UNSUPPORTED, "a grouped launch would exceed the grid limit; use schedule 1");
+  // upload and turn offsets into device pointers
+  const int64_t nbytes = static_cast<int64_t>(blob.bytes.size());
+  DPX_TRY(dev_alloc(reinterpret_cast<char**>(&p->d_tasks), nbytes, "grouped-launch tasks"));
+  DPX_HIP(hipMemcpy(p->d_tasks, blob.bytes.data(), static_cast<size_t>(nbytes), hipMemcpyHostToDevice));
+  p->bytes += nbytes;
+  char* base = static_cast<char*>(p->d_tasks);
+  auto fix = [&](std::vector<GroupLaunch>& v) {
+    for (auto& L : v) L.g.tasks = base + reinterpret_cast<uintptr_t>(L.g.tasks);
+  };
+  for (auto& v : p->g_fwd) fix(v);
+  for (auto& v : p->g_bwd) fix(v);
+  fix(p->g_loss);
+  p->d_loss_tasks = reinterpret_cast<const dpx::LossTask*>(base + loss_table);
+  return DPX_OK;
+}
+
+// Enqueues one list of grouped launches on s.  out_f: intensity (binning) or dL/dh (reduction).
+dpx_status run_groups(dpx_plan* p, const std::vector<GroupLaunch>& launches, const dpx::CallBuffers& call,
+                      float* out_f, hipStream_t s) {
+  for (const auto& L : launches) {
+    dpx::GroupArgs g = L.g;
+    g.call = call;
+    TimedLaunch t{L.pass, nullptr, nullptr, L.bytes + (call.u_in ? L.u_bytes : 0), L.flops};
+    const bool timed = (L.kind == GK_ROW || L.kind == GK_COL);
+    if (timed) DPX_TRY(timer_begin(p, s, t));
+    hipError_t e = hipErrorInvalidValue;
+    switch (L.kind) {
+      case GK_ROW: e = dpx::launch_row_group(L.M, L.pad, L.mode, g, s); break;
+      case GK_COL: e = dpx::launch_col_group(L.M, L.pad, L.conj, L.variant, g, s); break;
+      case GK_BIN: e = dpx::launch_bin_group(g, out_f, s); break;
+      case GK_DH: e = dpx::launch_dh_group(g, out_f, s); break;
+      case GK_LOSS: break;
+    }
+    if (e != hipSuccess) return fail(DPX_E_DEVICE, "grouped launch (kind %d, M %d) failed: %s",
+                                     static_cast<int>(L.kind), L.M, hipGetErrorString(e));
+    if (timed) DPX_TRY(timer_end(p, s, t));
   }
   return DPX_OK;
 }
@@ -536,6 +870,22 @@ dpx_status for_each_design(dpx_plan* p, hipStream_t s, F&& fn) {
   return DPX_OK;
 }
 
+// Runs the grouped launch lists of every partition, partition k on stream k (forked from and
+// joined back to s).
+dpx_status run_group_parts(dpx_plan* p, const std::vector<std::vector<GroupLaunch>>& parts,
+                           const dpx::CallBuffers& call, float* out_f, hipStream_t s) {
+  const int n = static_cast<int>(parts.size());
+  if (n <= 1) return n == 1 ? run_groups(p, parts[0], call, out_f, s) : DPX_OK;
+  DPX_HIP(hipEventRecord(p->ev_fork, s));
+  for (int k = 1; k < n; ++k) DPX_HIP(hipStreamWaitEvent(p->aux[k - 1], p->ev_fork, 0));
+  for (int k = 0; k < n; ++k) DPX_TRY(run_groups(p, parts[k], call, out_f, k == 0 ? s : p->aux[k - 1]));
+  for (int k = 1; k < n; ++k) {
+    DPX_HIP(hipEventRecord(p->ev_join[k - 1], p->aux[k - 1]));
+    DPX_HIP(hipStreamWaitEvent(s, p->ev_join[k - 1], 0));
+  }
+  return DPX_OK;
+}
+
 constexpr size_t kMaxGraphs = 16;
 
 // Runs `enqueue` on the caller's stream, or (opts.use_graph, timers off) replays a graph of
@@ -615,6 +965,12 @@ dpx_status dpx_plan_variant(const dpx_plan* p, int32_t i, int32_t* variant) {
   if (i < 0 || i >= static_cast<int>(p->designs.size()))
     return fail(DPX_E_ARG, "design index %d out of range", i);
   *variant = p->designs[i].col_variant;
+  return ok();
+}
+
+dpx_status dpx_plan_schedule(const dpx_plan* p, int32_t* schedule) {
+  if (!p || !schedule) return fail(DPX_E_ARG, "plan and schedule must not be NULL");
+  *schedule = p->grouped ? 2 : 1;
   return ok();
 }
 
@@ -712,6 +1068,17 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
       p->bytes += tb;
     }
   }
+  // grouped schedule: asked for, or automatic for several designs whose wavelengths are not
+  // split over chunk lanes (the grouped lists of up to four design partitions then run side by
+  // side, like single designs)
+  const bool try_group = o.schedule == 2 || (o.schedule == 0 && nd > 1 && o.streams <= 1);
+  if (st == DPX_OK && try_group) {
+    p->grouped = groupable(p);
+    if (!p->grouped && o.schedule == 2)
+      st = fail(DPX_E_UNSUPPORTED,
+                "the grouped schedule needs checkpoint_mode 0, every design in one wavelength chunk "
+                "on one stream, and a transform column variant (0-3)");
+  }
   if (st == DPX_OK) {
     int max_lanes = 1;
     for (const auto& d : p->designs) max_lanes = std::max(max_lanes, d.lanes);
@@ -780,6 +1147,11 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     for (auto& d : p->designs)
       if ((st = autotune_design(p, d, cache)) != DPX_OK) break;
   }
+  if (st == DPX_OK && p->grouped) {
+    // the autotuner may have picked the matrix-core column pass, which has no grouped form
+    if (groupable(p)) st = build_groups(p);
+    else p->grouped = false;
+  }
   if (st != DPX_OK) {
     std::string msg = g_last_error;
     dpx_plan_destroy(p);
@@ -800,6 +1172,7 @@ dpx_status dpx_plan_destroy(dpx_plan* p) {
   for (auto& d : p->designs) free_design(d);
   for (auto& kv : p->twiddles) hipFree(kv.second);
   for (auto& kv : p->dft) hipFree(kv.second);
+  if (p->d_tasks) hipFree(p->d_tasks);
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->gstream) (void)hipStreamDestroy(p->gstream);
   if (p->ev_gin) (void)hipEventDestroy(p->ev_gin);
@@ -852,6 +1225,8 @@ dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* in
   hipStream_t caller = static_cast<hipStream_t>(stream);
   p->fwd_valid = false;
   auto enqueue = [&](hipStream_t s0) -> dpx_status {
+    if (p->grouped)
+      return run_group_parts(p, p->g_fwd, {h, reinterpret_cast<const float2*>(u_in), nullptr}, intensity, s0);
     return for_each_design(p, s0, [&](const Design& d, int, hipStream_t s) -> dpx_status {
       DPX_TRY(fork_lanes(p, d, s));
       for (int c = 0; c < d.nchunks; ++c) {
@@ -889,6 +1264,15 @@ dpx_status dpx_loss(dpx_plan* p, const float* intensity, const float* target, do
   DPX_TRY(sticky_check());
   hipStream_t caller = static_cast<hipStream_t>(stream);
   auto enqueue = [&](hipStream_t s0) -> dpx_status {
+    if (p->grouped) {
+      for (const auto& L : p->g_loss) {
+        hipError_t e = dpx::launch_loss_group(L.g, intensity, target, dl_di, s0);
+        if (e != hipSuccess) return fail(DPX_E_DEVICE, "loss launch failed: %s", hipGetErrorString(e));
+      }
+      hipError_t e = dpx::launch_loss_sum_group(p->d_loss_tasks, static_cast<int>(p->designs.size()), loss, s0);
+      if (e != hipSuccess) return fail(DPX_E_DEVICE, "loss launch failed: %s", hipGetErrorString(e));
+      return DPX_OK;
+    }
     return for_each_design(p, s0, [&](const Design& d, int i, hipStream_t s) -> dpx_status {
       hipError_t e = dpx::launch_loss(intensity + d.img_off, target + d.img_off,
                                       dl_di ? dl_di + d.img_off : nullptr, d.per_wl, d.W, d.T, s);
@@ -916,6 +1300,8 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
                 "u_in");
   hipStream_t caller = static_cast<hipStream_t>(stream);
   auto enqueue = [&](hipStream_t s0) -> dpx_status {
+    if (p->grouped)
+      return run_group_parts(p, p->g_bwd, {h, reinterpret_cast<const float2*>(u_in), dl_di}, dl_dh, s0);
     return for_each_design(p, s0, [&](const Design& d, int, hipStream_t s) -> dpx_status {
       DPX_TRY(fork_lanes(p, d, s));
       for (int c = 0; c < d.nchunks; ++c) {

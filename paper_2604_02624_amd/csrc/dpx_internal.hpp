@@ -62,6 +62,72 @@ struct ColArgs {
   const float2* dft;         // DFT matrices of the transform (matrix-core variant only)
 };
 
+// ------------------------------------------------------------------------------------------
+// Grouped launches: one launch of a pass for several designs that share the transform length
+// (and pad, mode, column variant).  Each design is a task owning a contiguous run of blocks
+// of a one-dimensional grid; the first block of every task travels in the kernel argument
+// (kMaxGroupTasks per launch), the tasks' arguments in a device array built at plan
+// creation.  Buffers the caller passes per call (heights, input field, dL/dI, outputs) are
+// offsets in the tasks and base pointers in the launch.
+// ------------------------------------------------------------------------------------------
+constexpr int kMaxGroupTasks = 64;
+
+struct CallBuffers {
+  const float* h;            // packed heights (all designs)
+  const float2* u_in;        // packed input fields or null
+  const float* dl_di;        // packed dL/dI or null
+};
+
+struct GroupArgs {
+  const void* tasks;         // RowTask / ColTask / BinTask / LossTask / DhTask [ntasks]
+  CallBuffers call;
+  int ntasks;
+  int block0[kMaxGroupTasks + 1];  // first block of each task; block0[ntasks] = grid size
+};
+
+struct RowTask {
+  RowArgs a;                 // h, u_in, dl_di unset: taken from the call plus the offsets
+  int64_t h_off, u_off, img_off;
+  int gx;                    // row blocks (x extent of the design's own grid)
+  int nblocks;               // gx times the wavelength blocks
+};
+
+struct ColTask {
+  ColArgs a;
+  int gx;                    // column tiles
+  int nblocks;               // gx times the wavelength blocks
+};
+
+struct BinTask {
+  const float2* ofov;        // [W][F][F] window field
+  int64_t img_off;           // offset of the design's intensities in the packed output
+  int w_count, fov, bin;
+};
+
+struct LossTask {
+  int64_t img_off;           // offset of the design's images in the packed buffers
+  double* per_wl;            // [W] per-wavelength loss of the design
+  int W, T;
+};
+
+struct DhTask {
+  const float* part;         // [nslots][K][N][N] gradient slots
+  int64_t h_off;             // offset of the design's heights in the packed dL/dh
+  int64_t per;               // K N N
+  int nslots;
+};
+
+constexpr int kGroupThreads = 256;  // threads per block of the grouped binning / reduction
+
+hipError_t launch_row_group(int M, int pad, int mode, const GroupArgs& g, hipStream_t s);
+hipError_t launch_col_group(int M, int pad, bool conj, int variant, const GroupArgs& g, hipStream_t s);
+hipError_t launch_bin_group(const GroupArgs& g, float* out, hipStream_t s);
+hipError_t launch_loss_group(const GroupArgs& g, const float* I, const float* tau, float* dl_di,
+                             hipStream_t s);
+hipError_t launch_loss_sum_group(const LossTask* tasks, int ntasks, double* loss, hipStream_t s);
+hipError_t launch_dh_group(const GroupArgs& g, float* dl_dh, hipStream_t s);
+int col_tile_width(int M, int variant);  // columns per block of a transform variant (0-3)
+
 // launchers (dpx_kernels.hip); each returns a hipError_t from the launch
 hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,
                       hipStream_t s);

@@ -48,8 +48,10 @@ constexpr int row_block_threads() { return row_threads_of_mode(MODE); }
 // Row pass.  A block owns G = 256 / P consecutive rows (one transform group per row) and
 // loops over a run of wavelengths, so the row's heights stay in registers.
 // ------------------------------------------------------------------------------------------
+// Block (bx, by) of a row pass: rows row_lo + bx G .. + G - 1, wavelength block by.
+// lds_all: G exchange regions; tw: room for the twiddle table (both in LDS).
 template <int M, int PAD, int MODE>
-__global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs a) {
+__device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float2* lds_all, float2* tw) {
   constexpr int kRowThreads = row_block_threads<M, MODE>();
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
@@ -57,8 +59,6 @@ __global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs 
   constexpr int EN = E / PAD;  // registers that hold x < N
   constexpr bool HALF = (PAD == 2);
   constexpr int RG = Geo<M>::ROW_REGION;
-  __shared__ float2 lds_all[G * RG];
-  __shared__ float2 tw[twiddle_count<M>()];
   stage_twiddles<M>(tw, a.tw, threadIdx.x, kRowThreads);
   __syncthreads();
 
@@ -66,13 +66,13 @@ __global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs 
   const int g = threadIdx.x / P;
   const int j0 = threadIdx.x % P;
   float2* lds = lds_all + g * RG;
-  const int y_raw = a.row_lo + blockIdx.x * G + g;
+  const int y_raw = a.row_lo + bx * G + g;
   const bool active = y_raw < a.row_hi;
   const int y = active ? y_raw : a.row_lo;
   const size_t plane = static_cast<size_t>(N) * M;
   const size_t nn = static_cast<size_t>(N) * N;
 
-  const int wb = a.w_begin + blockIdx.y * a.w_per_block;
+  const int wb = a.w_begin + by * a.w_per_block;
   const int we = min(wb + a.w_per_block, a.w_begin + a.w_count);
 
   float hreg[EN];
@@ -193,10 +193,10 @@ __global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs 
       for (int t = 0; t < EN; ++t) {
         const float2 gv = reg[t];
         const float2 v = ck[j0 + P * t];
-        // conj(g) v
-        const float re = gv.x * v.x + gv.y * v.y;
-        const float im = gv.x * v.y - gv.y * v.x;
-        acc[t] += -ct * im - ca * re;
+        // conj(g) v; acc += -ct Im - ca Re
+        const float re = fmaf(gv.x, v.x, gv.y * v.y);
+        const float im = fmaf(gv.x, v.y, -(gv.y * v.x));
+        acc[t] = fmaf(-ct, im, fmaf(-ca, re, acc[t]));
         if constexpr (MODE == ROW_ADJ_MID) reg[t] = cmulc(gv, transmission(hreg[t], c));
       }
       if constexpr (MODE == ROW_ADJ_MID) {
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs 
     }
     if (active) {
       float* dst = a.dh_part +
-                   (static_cast<size_t>(a.chunk_base + blockIdx.y) * a.layers + a.layer) * nn +
+                   (static_cast<size_t>(a.chunk_base + by) * a.layers + a.layer) * nn +
                    static_cast<size_t>(y) * N;
       if (a.accumulate) {
 #pragma unroll
@@ -220,6 +220,43 @@ __global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs 
       }
     }
   }
+}
+
+template <int M, int PAD, int MODE>
+__global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs a) {
+  __shared__ float2 lds_all[row_block_threads<M, MODE>() / Geo<M>::P * Geo<M>::ROW_REGION];
+  __shared__ float2 tw[twiddle_count<M>()];
+  row_body<M, PAD, MODE>(a, blockIdx.x, blockIdx.y, lds_all, tw);
+}
+
+// Task of a grouped launch that block b belongs to: the last task whose first block is <= b
+// (the table of first blocks is a kernel argument, so the search runs on scalar loads).
+__device__ __forceinline__ int group_task(const GroupArgs& g, int b) {
+  int lo = 0, hi = g.ntasks;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (g.block0[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One launch of a row pass for several designs of the same transform length and mode: each
+// block finds its design's task, patches the per-call buffers into the design's arguments
+// and runs the same body as the single-design kernel.
+template <int M, int PAD, int MODE>
+__global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_group_kernel(GroupArgs g) {
+  __shared__ float2 lds_all[row_block_threads<M, MODE>() / Geo<M>::P * Geo<M>::ROW_REGION];
+  __shared__ float2 tw[twiddle_count<M>()];
+  const int ti = group_task(g, blockIdx.x);
+  const RowTask& t = static_cast<const RowTask*>(g.tasks)[ti];
+  const int local = static_cast<int>(blockIdx.x) - g.block0[ti];
+  if (local >= t.nblocks) return;  // alignment padding between tasks
+  RowArgs a = t.a;
+  a.h = g.call.h ? g.call.h + t.h_off : nullptr;
+  a.u_in = g.call.u_in ? g.call.u_in + t.u_off : nullptr;
+  a.dl_di = g.call.dl_di ? g.call.dl_di + t.img_off : nullptr;
+  row_body<M, PAD, MODE>(a, local % t.gx, local / t.gx, lds_all, tw);
 }
 
 // H(kx, ky) / M^2 with the conjugate for the adjoint; 0 outside the propagating disc
@@ -237,9 +274,10 @@ __device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
 // then runs forward FFT -> transfer function -> inverse FFT on its column in registers, and
 // the kept rows go back through the same LDS tile.
 // ------------------------------------------------------------------------------------------
+// Block (bx, by) of a column pass: column tile bx of gx, wavelength block by.  The blocks of
+// one pass are numbered bx + gx by from a multiple of 16 in launch order.
 template <int M, int PAD, bool CONJ, int TX, bool MIRROR>
-__global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_per_eu(4)))
-col_kernel(ColArgs a) {
+__device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int gx, float2* tile, float2* tw) {
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
   constexpr int NT = TX * P;
@@ -247,15 +285,13 @@ col_kernel(ColArgs a) {
   constexpr int EN = E / PAD;
   constexpr bool HALF = (PAD == 2);
   static_assert(NT / TX == P, "staging rows per pass");
-  __shared__ float2 tile[TX * LD];
-  __shared__ float2 tw[twiddle_count<M>()];
 
   const int N = M / PAD;
   // XCD-aware tile order: consecutive blocks go to the eight XCDs in turn, so blocks b and
   // b + 8 of every run of 16 share an XCD and its L2; giving them neighbouring column tiles
   // lets the two halves of each 128-byte row segment meet in the same L2.
-  int tile_x = blockIdx.x;
-  if ((gridDim.x & 15) == 0) {
+  int tile_x = bx;
+  if ((gx & 15) == 0) {
     const int r = tile_x & 15;
     tile_x = (tile_x & ~15) + ((r & 7) << 1) + (r >> 3);
   }
@@ -274,7 +310,7 @@ col_kernel(ColArgs a) {
   // the rows go straight to LDS.  Row k of a lane is one buffer load at the lane's 32-bit
   // byte offset plus the scalar offset k P M 8, so no per-row address stays live.
   constexpr bool PREFETCH = HALF;
-  const int wb = blockIdx.y * a.col_wpb;
+  const int wb = by * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
   const unsigned voff = static_cast<unsigned>(((a.in_lo + yy) * M + kx0 + cc) * 8);
   auto plane = [&](int w) {
@@ -360,6 +396,29 @@ col_kernel(ColArgs a) {
     for (int y = a.out_lo + yy; y < a.out_hi; y += P) sp[static_cast<size_t>(y) * M] = tile[cc * LD + y];
     __syncthreads();  // the next wavelength's staging overwrites the tile
   }
+}
+
+template <int M, int PAD, bool CONJ, int TX, bool MIRROR>
+__global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_per_eu(4)))
+col_kernel(ColArgs a) {
+  __shared__ float2 tile[TX * Geo<M>::COL_REGION];
+  __shared__ float2 tw[twiddle_count<M>()];
+  col_body<M, PAD, CONJ, TX, MIRROR>(a, blockIdx.x, blockIdx.y, gridDim.x, tile, tw);
+}
+
+// One launch of a column pass for several designs of the same transform length (see
+// row_group_kernel); every task starts at a multiple of 16 blocks.
+template <int M, int PAD, bool CONJ, int TX, bool MIRROR>
+__global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_per_eu(4)))
+col_group_kernel(GroupArgs g) {
+  __shared__ float2 tile[TX * Geo<M>::COL_REGION];
+  __shared__ float2 tw[twiddle_count<M>()];
+  const int ti = group_task(g, blockIdx.x);
+  const ColTask& t = static_cast<const ColTask*>(g.tasks)[ti];
+  const int local = static_cast<int>(blockIdx.x) - g.block0[ti];
+  if (local >= t.nblocks) return;
+  const ColArgs a = t.a;
+  col_body<M, PAD, CONJ, TX, MIRROR>(a, local % t.gx, local / t.gx, t.gx, tile, tw);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -495,10 +554,9 @@ __global__ void __launch_bounds__(gemm_threads(M)) colgemm_kernel(ColArgs a, con
 // ------------------------------------------------------------------------------------------
 // Small kernels
 // ------------------------------------------------------------------------------------------
-__global__ void bin_intensity_kernel(const float2* __restrict__ ofov, float* __restrict__ out,
-                                     int w_count, int fov, int bin) {
+__device__ __forceinline__ void bin_intensity_body(const float2* __restrict__ ofov, float* __restrict__ out,
+                                                   int w_count, int fov, int bin, size_t i) {
   const int T = fov / bin;
-  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const size_t total = static_cast<size_t>(w_count) * T * T;
   if (i >= total) return;
   const int w = static_cast<int>(i / (static_cast<size_t>(T) * T));
@@ -509,9 +567,23 @@ __global__ void bin_intensity_kernel(const float2* __restrict__ ofov, float* __r
   for (int a = 0; a < bin; ++a)
     for (int b = 0; b < bin; ++b) {
       const float2 v = o[static_cast<size_t>(ty * bin + a) * fov + tx * bin + b];
-      s += v.x * v.x + v.y * v.y;
+      s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
     }
   out[i] = s;
+}
+
+__global__ void bin_intensity_kernel(const float2* __restrict__ ofov, float* __restrict__ out,
+                                     int w_count, int fov, int bin) {
+  bin_intensity_body(ofov, out, w_count, fov, bin, static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+// grouped: task = one design's window fields -> its intensities in the packed output
+__global__ void bin_group_kernel(GroupArgs g, float* __restrict__ out) {
+  const int ti = group_task(g, blockIdx.x);
+  const BinTask& t = static_cast<const BinTask*>(g.tasks)[ti];
+  const int local = static_cast<int>(blockIdx.x) - g.block0[ti];
+  bin_intensity_body(t.ofov, out + t.img_off, t.w_count, t.fov, t.bin,
+                     static_cast<size_t>(local) * blockDim.x + threadIdx.x);
 }
 
 constexpr int kLossThreads = 256;
@@ -528,12 +600,10 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// One block per wavelength: sums in double in a fixed tree order (bitwise reproducible).
-__global__ void __launch_bounds__(kLossThreads)
-loss_kernel(const float* __restrict__ I, const float* __restrict__ tau, float* __restrict__ dl_di,
-            double* __restrict__ per_wl, int W, int T) {
-  __shared__ double sh[kLossThreads];
-  const int w = blockIdx.x;
+// One block per wavelength w: sums in double in a fixed tree order (bitwise reproducible).
+__device__ __forceinline__ void loss_body(const float* __restrict__ I, const float* __restrict__ tau,
+                                          float* __restrict__ dl_di, double* __restrict__ per_wl,
+                                          int W, int T, int w, double* sh) {
   const int P = T * T;
   const float* Iw = I + static_cast<size_t>(w) * P;
   const float* tw = tau + static_cast<size_t>(w) * P;
@@ -568,21 +638,65 @@ loss_kernel(const float* __restrict__ I, const float* __restrict__ tau, float* _
 }
 
 __global__ void __launch_bounds__(kLossThreads)
-loss_sum_kernel(const double* __restrict__ per_wl, double* __restrict__ loss, int W) {
+loss_kernel(const float* __restrict__ I, const float* __restrict__ tau, float* __restrict__ dl_di,
+            double* __restrict__ per_wl, int W, int T) {
   __shared__ double sh[kLossThreads];
+  loss_body(I, tau, dl_di, per_wl, W, T, blockIdx.x, sh);
+}
+
+// grouped: task = one design, one block per wavelength of every design
+__global__ void __launch_bounds__(kLossThreads)
+loss_group_kernel(GroupArgs g, const float* __restrict__ I, const float* __restrict__ tau,
+                  float* __restrict__ dl_di) {
+  __shared__ double sh[kLossThreads];
+  const int ti = group_task(g, blockIdx.x);
+  const LossTask& t = static_cast<const LossTask*>(g.tasks)[ti];
+  const int w = static_cast<int>(blockIdx.x) - g.block0[ti];
+  loss_body(I + t.img_off, tau + t.img_off, dl_di ? dl_di + t.img_off : nullptr, t.per_wl, t.W, t.T, w, sh);
+}
+
+__device__ __forceinline__ void loss_sum_body(const double* __restrict__ per_wl, double* __restrict__ loss,
+                                              int W, double* sh) {
   double s = 0.0;
   for (int w = threadIdx.x; w < W; w += kLossThreads) s += per_wl[w];
   const double tot = block_sum(s, sh);
   if (threadIdx.x == 0) *loss = tot / W;
 }
 
-__global__ void dh_reduce_kernel(const float* __restrict__ part, float* __restrict__ dh, int nchunk,
-                                 int64_t per_chunk) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kLossThreads)
+loss_sum_kernel(const double* __restrict__ per_wl, double* __restrict__ loss, int W) {
+  __shared__ double sh[kLossThreads];
+  loss_sum_body(per_wl, loss, W, sh);
+}
+
+// grouped: block i = design i of the plan (tasks in design order)
+__global__ void __launch_bounds__(kLossThreads)
+loss_sum_group_kernel(const LossTask* __restrict__ tasks, double* __restrict__ loss) {
+  __shared__ double sh[kLossThreads];
+  const LossTask& t = tasks[blockIdx.x];
+  loss_sum_body(t.per_wl, loss + blockIdx.x, t.W, sh);
+}
+
+__device__ __forceinline__ void dh_reduce_body(const float* __restrict__ part, float* __restrict__ dh,
+                                               int nchunk, int64_t per_chunk, int64_t i) {
   if (i >= per_chunk) return;
   double s = 0.0;
   for (int c = 0; c < nchunk; ++c) s += part[c * per_chunk + i];
   dh[i] = static_cast<float>(s);
+}
+
+__global__ void dh_reduce_kernel(const float* __restrict__ part, float* __restrict__ dh, int nchunk,
+                                 int64_t per_chunk) {
+  dh_reduce_body(part, dh, nchunk, per_chunk, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+// grouped: task = one design's gradient slots -> its dL/dh in the packed output
+__global__ void dh_group_kernel(GroupArgs g, float* __restrict__ dl_dh) {
+  const int ti = group_task(g, blockIdx.x);
+  const DhTask& t = static_cast<const DhTask*>(g.tasks)[ti];
+  const int local = static_cast<int>(blockIdx.x) - g.block0[ti];
+  dh_reduce_body(t.part, dl_dh + t.h_off, t.nslots, t.per,
+                 static_cast<int64_t>(local) * blockDim.x + threadIdx.x);
 }
 
 __global__ void fill_zero_kernel(float* p, int64_t n) {
@@ -725,7 +839,7 @@ static hipError_t col_launch(bool conj, const ColArgs& a, int w_count, hipStream
 template <int M, int PAD>
 static hipError_t col_dispatch_variant(int variant, bool conj, const ColArgs& a, int w_count,
                                        hipStream_t s) {
-  const bool t8 = (variant == 0 || variant == 2) && 8 * Geo<M>::P >= 64;
+  const bool t8 = col_tile_width(M, variant) == 8;
   const bool mirror = variant >= 2;
   if (t8) return mirror ? col_launch<M, PAD, 8, true>(conj, a, w_count, s)
                         : col_launch<M, PAD, 8, false>(conj, a, w_count, s);
@@ -811,6 +925,99 @@ hipError_t launch_dh_reduce(const float* part, float* dh, int nchunk, int64_t pe
   const int th = 256;
   dh_reduce_kernel<<<static_cast<unsigned>((per_chunk + th - 1) / th), th, 0, s>>>(part, dh, nchunk,
                                                                                  per_chunk);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Grouped launchers: the grid is block0[ntasks] blocks
+// ------------------------------------------------------------------------------------------
+static unsigned group_grid(const GroupArgs& g) { return static_cast<unsigned>(g.block0[g.ntasks]); }
+
+template <int M, int PAD>
+static hipError_t row_group_mode(int mode, const GroupArgs& g, hipStream_t s) {
+  switch (mode) {
+#define DPX_ROW(MD) \
+  case MD: row_group_kernel<M, PAD, MD><<<group_grid(g), row_block_threads<M, MD>(), 0, s>>>(g); break;
+    DPX_ROW(ROW_FWD_FIRST)
+    DPX_ROW(ROW_FWD_MID)
+    DPX_ROW(ROW_FWD_LAST)
+    DPX_ROW(ROW_ADJ_SEED)
+    DPX_ROW(ROW_ADJ_MID)
+    DPX_ROW(ROW_ADJ_LAST)
+#undef DPX_ROW
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_row_group(int M, int pad, int mode, const GroupArgs& g, hipStream_t s) {
+  if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks) return hipErrorInvalidValue;
+  switch (M) {
+#define DPX_CASE(m) \
+  case m: return pad == 2 ? row_group_mode<m, 2>(mode, g, s) : pad == 1 ? row_group_mode<m, 1>(mode, g, s) : hipErrorInvalidValue;
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+int col_tile_width(int M, int variant) {
+  const int P = row_lanes_per_transform(M);
+  return ((variant == 0 || variant == 2) && 8 * P >= 64) ? 8 : 16;
+}
+
+template <int M, int PAD, int TX, bool MIRROR>
+static hipError_t col_group_tx(bool conj, const GroupArgs& g, hipStream_t s) {
+  if (conj)
+    col_group_kernel<M, PAD, true, TX, MIRROR><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+  else
+    col_group_kernel<M, PAD, false, TX, MIRROR><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+template <int M, int PAD>
+static hipError_t col_group_variant(int variant, bool conj, const GroupArgs& g, hipStream_t s) {
+  const bool t8 = col_tile_width(M, variant) == 8;
+  const bool mirror = variant >= 2;
+  if (t8) return mirror ? col_group_tx<M, PAD, 8, true>(conj, g, s) : col_group_tx<M, PAD, 8, false>(conj, g, s);
+  return mirror ? col_group_tx<M, PAD, 16, true>(conj, g, s) : col_group_tx<M, PAD, 16, false>(conj, g, s);
+}
+
+hipError_t launch_col_group(int M, int pad, bool conj, int variant, const GroupArgs& g, hipStream_t s) {
+  if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks || variant < 0 || variant > 3) return hipErrorInvalidValue;
+  switch (M) {
+#define DPX_CASE(m) \
+  case m: return pad == 2 ? col_group_variant<m, 2>(variant, conj, g, s) : pad == 1 ? col_group_variant<m, 1>(variant, conj, g, s) : hipErrorInvalidValue;
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bin_group(const GroupArgs& g, float* out, hipStream_t s) {
+  if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks) return hipErrorInvalidValue;
+  bin_group_kernel<<<group_grid(g), kGroupThreads, 0, s>>>(g, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_group(const GroupArgs& g, const float* I, const float* tau, float* dl_di,
+                             hipStream_t s) {
+  if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks) return hipErrorInvalidValue;
+  loss_group_kernel<<<group_grid(g), kLossThreads, 0, s>>>(g, I, tau, dl_di);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_sum_group(const LossTask* tasks, int ntasks, double* loss, hipStream_t s) {
+  if (ntasks < 1) return hipErrorInvalidValue;
+  loss_sum_group_kernel<<<ntasks, kLossThreads, 0, s>>>(tasks, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_dh_group(const GroupArgs& g, float* dl_dh, hipStream_t s) {
+  if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks) return hipErrorInvalidValue;
+  dh_group_kernel<<<group_grid(g), kGroupThreads, 0, s>>>(g, dl_dh);
   return hipGetLastError();
 }
 

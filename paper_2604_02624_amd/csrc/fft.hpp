@@ -27,9 +27,10 @@ namespace dpx {
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-// Complex products are written with explicit fused multiply-adds so that their rounding does
-// not depend on how the compiler contracts the surrounding code: the same operands give the
-// same bits in every kernel variant.
+// The library is built without floating-point contraction (-ffp-contract=off): every fused
+// multiply-add is written out (fmaf), so the rounding of each value is fixed by the source and
+// the same operands give the same bits in every kernel that inlines this code (every column
+// variant, grouped and per-design launches).
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
@@ -111,8 +112,34 @@ __device__ __forceinline__ float2 twc(float2 v) {
   } else {
     constexpr float c = static_cast<float>(cos2pi(e, R));
     constexpr float s = static_cast<float>(INV ? sin2pi(e, R) : -sin2pi(e, R));
-    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+    return make_float2(fmaf(v.x, c, -(v.y * s)), fmaf(v.x, s, v.y * c));
   }
+}
+
+// W_R^E is an odd multiple of pi/4, i.e. (+-1 +- i) / sqrt(2)
+template <int R, int E>
+constexpr bool odd_octant() {
+  constexpr int e = ((E % R) + R) % R;
+  return e != 0 && (8 * e) % R == 0 && ((8 * e) / R) % 2 == 1;
+}
+
+// sqrt(2) v W_R^E for an odd octant: the rotation without its 1/sqrt(2), which the consumer
+// applies inside its own fused multiply-adds
+template <int R, int E, bool INV>
+__device__ __forceinline__ float2 twc_octant_unscaled(float2 v) {
+  constexpr int e = ((E % R) + R) % R;
+  constexpr int oct = (8 * e) / R;
+  constexpr int o = INV ? (8 - oct) % 8 : oct;
+  static_assert(o % 2 == 1, "odd octants only");
+  if constexpr (o == 1) return make_float2(v.x + v.y, v.y - v.x);
+  else if constexpr (o == 3) return make_float2(v.y - v.x, -(v.x + v.y));
+  else if constexpr (o == 5) return make_float2(-(v.x + v.y), v.x - v.y);
+  else return make_float2(v.x - v.y, v.x + v.y);  // o == 7
+}
+
+// s x + y per component
+__device__ __forceinline__ float2 cfma(float s, float2 x, float2 y) {
+  return make_float2(fmaf(s, x.x, y.x), fmaf(s, x.y, y.y));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -143,12 +170,11 @@ struct DFT<3, INV, HALF> {
     constexpr float s = INV ? 0.86602540378443864676f : -0.86602540378443864676f;
     float2 a = v[0], b = v[1], d = v[2];
     float2 sum = cadd(b, d), dif = csub(b, d);
-    float2 m = make_float2(a.x + c * sum.x, a.y + c * sum.y);
-    // i s (b - d)
-    float2 r = make_float2(-s * dif.y, s * dif.x);
+    float2 m = make_float2(fmaf(c, sum.x, a.x), fmaf(c, sum.y, a.y));
+    // m +- i s (b - d)
     v[0] = cadd(a, sum);
-    v[1] = cadd(m, r);
-    v[2] = csub(m, r);
+    v[1] = make_float2(fmaf(-s, dif.y, m.x), fmaf(s, dif.x, m.y));
+    v[2] = make_float2(fmaf(s, dif.y, m.x), fmaf(-s, dif.x, m.y));
   }
 };
 
@@ -166,6 +192,48 @@ struct DFT<4, INV, HALF> {
       float2 a = v[0], b = v[1], c = v[2], d = v[3];
       float2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = csub(b, d);
       float2 id1 = INV ? mul_posi(d1) : mul_negi(d1);
+      v[0] = cadd(s0, s1);
+      v[2] = csub(s0, s1);
+      v[1] = cadd(d0, id1);
+      v[3] = csub(d0, id1);
+    }
+  }
+};
+
+// 4-point DFT whose inputs 1..3 carry a pending factor 1/sqrt(2) where bit n of SM is set
+// (they come from odd-octant twiddles): the factor is folded into the butterfly's additions.
+template <bool INV, int SM>
+struct DFT4Scaled {
+  static_assert((SM & 1) == 0, "input 0 is never scaled");
+  static __device__ __forceinline__ void run(float2* v) {
+    constexpr float h = 0.70710678118654752440f;
+    constexpr bool fb = (SM & 2) != 0, fc = (SM & 4) != 0, fd = (SM & 8) != 0;
+    const float2 a = v[0], b = v[1], c = v[2], d = v[3];
+    float2 s0, d0, s1, d1;
+    if constexpr (fc) {
+      s0 = cfma(h, c, a);
+      d0 = cfma(-h, c, a);
+    } else {
+      s0 = cadd(a, c);
+      d0 = csub(a, c);
+    }
+    if constexpr (fb && !fd) {
+      s1 = cfma(h, b, d);
+      d1 = cfma(h, b, make_float2(-d.x, -d.y));
+    } else if constexpr (fd && !fb) {
+      s1 = cfma(h, d, b);
+      d1 = cfma(-h, d, b);
+    } else {  // both scaled (the sums keep the factor) or neither
+      s1 = cadd(b, d);
+      d1 = csub(b, d);
+    }
+    const float2 id1 = INV ? mul_posi(d1) : mul_negi(d1);
+    if constexpr (fb && fd) {
+      v[0] = cfma(h, s1, s0);
+      v[2] = cfma(-h, s1, s0);
+      v[1] = cfma(h, id1, d0);
+      v[3] = cfma(-h, id1, d0);
+    } else {
       v[0] = cadd(s0, s1);
       v[2] = csub(s0, s1);
       v[1] = cadd(d0, id1);
@@ -195,7 +263,11 @@ struct DFT {
       DFT<A, INV, HALF>::run(t);
       static_for<0, A>([&](auto k1c) {
         constexpr int k1 = decltype(k1c)::value;
-        y[n2 * A + k1] = twc<R, n2 * k1, INV>(t[k1]);
+        // with B = 4 the 1/sqrt(2) of odd-octant twiddles is left to the 4-point butterfly
+        if constexpr (B == 4 && odd_octant<R, n2 * k1>())
+          y[n2 * A + k1] = twc_octant_unscaled<R, n2 * k1, INV>(t[k1]);
+        else
+          y[n2 * A + k1] = twc<R, n2 * k1, INV>(t[k1]);
       });
     });
     static_for<0, A>([&](auto k1c) {
@@ -205,7 +277,13 @@ struct DFT {
         constexpr int n2 = decltype(n2c)::value;
         t[n2] = y[n2 * A + k1];
       });
-      DFT<B, INV, false>::run(t);
+      if constexpr (B == 4) {
+        constexpr int SM = (odd_octant<R, 1 * k1>() ? 2 : 0) | (odd_octant<R, 2 * k1>() ? 4 : 0) |
+                           (odd_octant<R, 3 * k1>() ? 8 : 0);
+        DFT4Scaled<INV, SM>::run(t);
+      } else {
+        DFT<B, INV, false>::run(t);
+      }
       static_for<0, B>([&](auto k2c) {
         constexpr int k2 = decltype(k2c)::value;
         v[k1 + A * k2] = t[k2];

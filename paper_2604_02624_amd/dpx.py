@@ -34,7 +34,7 @@ class COpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("force_variant", ctypes.c_int32), ("check_finite", ctypes.c_int32),
                 ("max_workspace_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32)]
 
 
 class CLayout(ctypes.Structure):
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.dpx_variant_name.restype = ctypes.c_char_p
     lib.dpx_plan_variant.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.dpx_plan_variant.restype = ctypes.c_int
+    lib.dpx_plan_schedule.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.dpx_plan_schedule.restype = ctypes.c_int
     lib.dpx_timing_enable.argtypes = [vp, i32]
     lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -124,7 +126,7 @@ def _c_designs(designs):
 
 
 def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
-          autotune=0, streams=0, use_graph=0):
+          autotune=0, streams=0, use_graph=0, schedule=0):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
@@ -134,6 +136,7 @@ def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_by
     o.streams = int(streams)
     o.use_graph = int(use_graph)
     o.max_workspace_bytes = max_workspace_bytes
+    o.schedule = int(schedule)
     return o
 
 
@@ -169,7 +172,7 @@ class Plan:
 
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
                  force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False,
-                 streams: int = 0, use_graph: bool = False):
+                 streams: int = 0, use_graph: bool = False, schedule: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
@@ -177,7 +180,7 @@ class Plan:
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
         o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune,
-                  streams, use_graph)
+                  streams, use_graph, schedule)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))
@@ -204,6 +207,12 @@ class Plan:
         v = ctypes.c_int32()
         _check(self.lib, self.lib.dpx_plan_variant(self._h, i, ctypes.byref(v)))
         return v.value
+
+    def schedule(self) -> int:
+        """1: one launch per design and pass; 2: grouped launches over designs."""
+        v = ctypes.c_int32(0)
+        _check(self.lib, self.lib.dpx_plan_schedule(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def layout(self, i: int) -> dict:
         lo = CLayout()

@@ -110,6 +110,9 @@ def test_query_rejects_bad_options(lib):
         _query([d], checkpoint_mode=2)
     with pytest.raises(dpx.DpxError):
         _query([d], force_variant=5)
+    with pytest.raises(dpx.DpxError):
+        _query([d], schedule=3)
+    assert _query([d], schedule=2) > 0
 
 
 def test_null_plan_and_pointers_are_errors(lib):

@@ -383,16 +383,74 @@ def test_graph_replay_matches_direct_launches(torch_dev):
 
 
 def test_concurrent_designs_match_sequential(torch_dev):
-    say("uneven designs on several streams vs one stream")
+    say("uneven designs: several streams and grouped launches vs one design at a time")
     w = wk.make_workload(5)
     ds, hs, taus = w["designs"][:12], w["h"][:12], w["targets"][:12]
-    seq = run_gpu(torch_dev, ds, hs, taus, streams=1)
-    par = run_gpu(torch_dev, ds, hs, taus)
-    par2 = run_gpu(torch_dev, ds, hs, taus, use_graph=True)
-    for r in (par, par2):
+    seq = run_gpu(torch_dev, ds, hs, taus, streams=1, schedule=1)
+    par = run_gpu(torch_dev, ds, hs, taus, schedule=1)
+    par2 = run_gpu(torch_dev, ds, hs, taus, schedule=1, use_graph=True)
+    grp = run_gpu(torch_dev, ds, hs, taus)
+    grp2 = run_gpu(torch_dev, ds, hs, taus, use_graph=True)
+    assert seq["plan"].schedule() == 1 and grp["plan"].schedule() == 2
+    for r in (par, par2, grp, grp2):
         assert torch_dev.equal(r["I"], seq["I"])
         assert torch_dev.equal(r["L"], seq["L"])
         assert torch_dev.equal(r["dh"], seq["dh"])
+
+
+def _mixed_designs(rng):
+    """Designs that exercise every key of the grouped schedule: both pads, one transform
+    length reached from two N, 1-4 layers, input fields, absorption, binning."""
+    specs = [  # n, layers, W, fov, bin, pad
+        (64, 3, 4, 32, 2, 2), (128, 2, 3, 64, 1, 1), (64, 1, 5, 64, 1, 2), (48, 4, 2, 24, 3, 2),
+        (96, 2, 3, 48, 2, 2), (64, 2, 6, 16, 1, 2), (32, 3, 7, 16, 2, 2), (128, 1, 2, 32, 4, 1),
+    ]
+    ds, hs, us, taus = [], [], [], []
+    for i, (n, k, W, f, b, pad) in enumerate(specs):
+        wl = np.linspace(470e-9, 720e-9, W)
+        ds.append(wk.make_design(n=n, layers=k, wl=wl, n_mat=wk.cauchy_index(wl), dx=280e-9,
+                                 z=list(np.linspace(8e-6, 14e-6, k)), fov=f, bin_=b, pad=pad,
+                                 kappa=np.linspace(0.0, 0.02, W) if i % 2 else None))
+        hs.append((rng.random((k, n, n)) * 1.1e-6).astype(np.float32))
+        us.append((rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64))
+        taus.append(rng.random((W, f // b, f // b)).astype(np.float32))
+    return ds, hs, us, taus
+
+
+def test_grouped_schedule_mixed_designs(torch_dev):
+    say("grouped schedule vs per design: mixed pads, lengths, layers, u_in, kappa, bins")
+    ds, hs, us, taus = _mixed_designs(np.random.default_rng(77))
+    ref = run_gpu(torch_dev, ds, hs, taus, u_ins=us, schedule=1, streams=1)
+    grp = run_gpu(torch_dev, ds, hs, taus, u_ins=us, schedule=2)
+    assert grp["plan"].schedule() == 2
+    assert torch_dev.equal(grp["I"], ref["I"])
+    assert torch_dev.equal(grp["L"], ref["L"])
+    assert torch_dev.equal(grp["g"], ref["g"])
+    assert torch_dev.equal(grp["dh"], ref["dh"])
+    # and one of them against the oracle (input field + absorption + bins)
+    i = 3
+    I_ref = o.forward(ds[i], hs[i], us[i], "fft")
+    Is = grp["plan"].unpack_images(grp["I"].cpu())
+    assert per_wl_rel(Is[i].numpy(), I_ref).max() <= INT_TOL
+
+
+def test_grouped_schedule_splits_large_groups(torch_dev):
+    say("grouped schedule: 70 designs of one transform length (two launches per pass)")
+    rng = np.random.default_rng(70)
+    ds, hs, taus = [], [], []
+    for i in range(70):
+        W = 1 + i % 4
+        wl = np.linspace(500e-9, 650e-9, W)
+        ds.append(wk.make_design(n=32, layers=2, wl=wl, n_mat=1.5, dx=300e-9, z=[6e-6, 9e-6],
+                                 fov=16, pad=2))
+        hs.append((rng.random((2, 32, 32)) * 1.2e-6).astype(np.float32))
+        taus.append(rng.random((W, 16, 16)).astype(np.float32))
+    ref = run_gpu(torch_dev, ds, hs, taus, schedule=1, streams=1)
+    grp = run_gpu(torch_dev, ds, hs, taus)
+    assert grp["plan"].schedule() == 2
+    assert torch_dev.equal(grp["I"], ref["I"])
+    assert torch_dev.equal(grp["L"], ref["L"])
+    assert torch_dev.equal(grp["dh"], ref["dh"])
 
 
 def test_error_paths(torch_dev):
@@ -417,6 +475,10 @@ def test_error_paths(torch_dev):
     with pytest.raises(dpx.DpxError) as e:
         dpx.Plan(w["designs"], max_workspace_bytes=1024)
     assert e.value.status == dpx.DPX_E_NOMEM
+    with pytest.raises(dpx.DpxError) as e:
+        dpx.Plan(w["designs"], schedule=2, checkpoint_mode=1)
+    assert e.value.status == dpx.DPX_E_UNSUPPORTED
+    assert dpx.Plan(w["designs"]).schedule() == 1        # one design: per-design launches
     torch_dev.cuda.synchronize()
 
 
