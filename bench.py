@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--checkpoint-mode", type=int, default=0, choices=[0, 1])
     ap.add_argument("--wl-chunk", type=int, default=0)
     ap.add_argument("--streams", type=int, default=0, help="concurrent chunk lanes (0 automatic)")
+    ap.add_argument("--transfer-table", type=int, default=0, choices=[0, 1, 2],
+                    help="transfer-function tables: 0 automatic, 1 never, 2 always")
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
                     help="several designs: 0 automatic, 1 per design, 2 grouped launches")
     ap.add_argument("--graph", action="store_true",
@@ -168,7 +170,7 @@ def main():
     designs = w["designs"]
     plan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
                     force_variant=args.variant, autotune=args.autotune, streams=args.streams,
-                    use_graph=args.graph, schedule=args.schedule)
+                    use_graph=args.graph, schedule=args.schedule, transfer_table=args.transfer_table)
     variant = dpx.variant_names()[plan.variant(0)]
     log(f"[bench] column-pass variant {variant}")
     h = plan.pack_heights(w["h"])
@@ -281,6 +283,7 @@ def main():
                     transform=d0["n"] * d0["pad"], checkpoint_mode=args.checkpoint_mode,
                     wl_chunk=args.wl_chunk, streams=args.streams, graph=args.graph,
                     schedule={1: "per-design", 2: "grouped"}[plan.schedule()],
+                    transfer_tables=plan.has_transfer_tables(),
                     column_variant=variant,
                     phase_args="f64"),
         roofline=roofline, cpu_baseline=cpu, plain_loop=plain,

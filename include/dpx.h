@@ -107,7 +107,14 @@ typedef struct dpx_opts {
                                (DFT as complex matrix products on the FP32 matrix cores,
                                transform lengths up to 512) agrees with them to rounding.
                                DPX_E_UNSUPPORTED if the variant is not built for a design. */
-  int32_t check_finite;     /* reserved */
+  int32_t transfer_table;   /* transfer function H(|kx|, |ky|) / M^2 of every wavelength and
+                               distinct gap precomputed at plan creation ((M/2+1)^2 complex
+                               values per wavelength and gap) and read by the column passes:
+                               0 = automatic (currently never: on MI355X the table reads
+                               cost the column pass more than the evaluation they replace),
+                               1 = never (evaluated in the column pass), 2 = always.
+                               The table holds the values the column pass would evaluate, so
+                               results are bitwise identical either way. */
   int64_t max_workspace_bytes; /* 0 = no limit; otherwise plan creation fails with
                                   DPX_E_NOMEM if the plan would need more */
   int32_t streams;          /* wavelength chunks processed concurrently on this many streams
@@ -141,6 +148,9 @@ typedef struct dpx_layout {
   int32_t transform_len;           /* M = pad * N */
   int32_t target_side;             /* T = fov / bin */
   int64_t workspace_bytes;         /* device bytes the plan holds for this design */
+  int32_t transfer_tables;         /* transfer tables held for this design (one per distinct
+                                      gap; 0 = H is evaluated in the column passes) */
+  int32_t reserved;
 } dpx_layout;
 
 typedef struct dpx_plan dpx_plan;

@@ -22,22 +22,28 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # do not depend on how a kernel inlines the shared code
           "-ffp-contract=off",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-SOURCES = ["dpx_kernels.hip", "dpx_api.cpp"]
+# transform lengths with their own translation unit of pass kernels (dpx_pass.hip)
+LENGTHS = [64, 96, 128, 192, 256, 384, 512, 1024]
+# (source, object name, extra flags); the long-running pass units first
+UNITS = ([("dpx_pass.hip", f"dpx_pass_{m}.o", [f"-DDPX_M={m}"]) for m in sorted(LENGTHS, reverse=True)]
+         + [("dpx_kernels.hip", "dpx_kernels.o", []), ("dpx_api.cpp", "dpx_api.o", [])])
 
 
-def _compile(src):
-    out = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", out]
+def _compile(unit):
+    src, obj, extra = unit
+    out = os.path.join(BUILD, obj)
+    cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        raise RuntimeError(f"compile of {src} {' '.join(extra)} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return out
 
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    workers = max(1, min(len(UNITS), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 4)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -62,7 +62,13 @@ struct Design {
   int nslots;        // lanes * slots_per_lane
   int row_group;     // rows per row-pass block
   int col_variant;   // column-pass kernel variant
+  // transfer-function tables: one [W][M/2+1][M/2+1] table per distinct gap; zslot[l] is the
+  // table of layer l's gap (empty: H is evaluated in the column pass)
+  int nzslots = 0;
+  std::vector<int> zslot;
+  int64_t table_bytes = 0;
   // device memory
+  float2* htab = nullptr;
   WlConst* d_wl = nullptr;
   float2* spec = nullptr;
   float2* ckpt = nullptr;
@@ -95,6 +101,7 @@ struct GroupLaunch {
   GroupKind kind;
   int M = 0, pad = 0, mode = 0, variant = 0;
   bool conj = false;
+  bool table = false;      // column launches: the tasks read transfer tables
   dpx::GroupArgs g{};
   int pass = -1;           // DPX_PASS_* of row / column launches (timers)
   int64_t bytes = 0;       // algorithmic bytes (without the input field)
@@ -152,6 +159,8 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
     if (o->wl_chunk < 0) return fail(DPX_E_ARG, "wl_chunk must be >= 0");
     if (o->streams < 0 || o->streams > 8) return fail(DPX_E_ARG, "streams must be in [0, 8]");
     if (o->schedule < 0 || o->schedule > 2) return fail(DPX_E_ARG, "schedule must be 0, 1 or 2");
+    if (o->transfer_table < 0 || o->transfer_table > 2)
+      return fail(DPX_E_ARG, "transfer_table must be 0, 1 or 2");
     if (o->max_workspace_bytes < 0) return fail(DPX_E_ARG, "max_workspace_bytes must be >= 0");
     if (o->force_variant < -1 || o->force_variant >= dpx::kColVariants)
       return fail(DPX_E_ARG, "force_variant must be -1 or a variant index below %d", dpx::kColVariants);
@@ -235,6 +244,24 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   d.slots_per_lane = (chunk + wpb - 1) / wpb;
   d.nslots = d.lanes * d.slots_per_lane;
   d.col_variant = o.force_variant >= 0 ? o.force_variant : dpx::default_col_variant(d.M);
+  // transfer tables (opts.transfer_table: 2 = always; 0 automatic and 1 = never: measured on
+  // MI355X, reading H costs the column pass more load traffic and latency than evaluating it
+  // saves arithmetic)
+  d.table_bytes = 0;
+  {
+    std::vector<double> zs;
+    d.zslot.assign(d.K, 0);
+    for (int l = 0; l < d.K; ++l) {
+      int k = 0;
+      while (k < static_cast<int>(zs.size()) && zs[k] != src.z[l]) ++k;
+      if (k == static_cast<int>(zs.size())) zs.push_back(src.z[l]);
+      d.zslot[l] = k;
+    }
+    const int64_t hs = d.M / 2 + 1;
+    const int64_t tb = static_cast<int64_t>(zs.size()) * d.W * hs * hs * 8;
+    d.nzslots = static_cast<int>(zs.size());
+    d.table_bytes = tb;
+  }
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
   const int ck_w = (o.checkpoint_mode == 1) ? d.lanes * d.wl_chunk : d.W;
   const int of_w = ck_w;
@@ -244,6 +271,14 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
             + static_cast<int64_t>(d.nslots) * d.K * nn * 4   // dL/dh partials
             + static_cast<int64_t>(d.W) * 8                   // per-wavelength loss
             + static_cast<int64_t>(d.W) * sizeof(WlConst);
+  const bool want = o.transfer_table == 2;
+  if (want) {
+    d.bytes += d.table_bytes;
+  } else {
+    d.table_bytes = 0;
+    d.nzslots = 0;
+    d.zslot.clear();
+  }
 }
 
 void free_design(Design& d) {
@@ -253,6 +288,8 @@ void free_design(Design& d) {
   hipFree(d.ofov);
   hipFree(d.dh_part);
   hipFree(d.per_wl);
+  hipFree(d.htab);
+  d.htab = nullptr;
   d.d_wl = nullptr;
   d.spec = d.ckpt = d.ofov = nullptr;
   d.dh_part = nullptr;
@@ -417,11 +454,17 @@ ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0
   // is transformed; measured best of 1, 2, 4, 8 on the large workload) when that still
   // leaves several blocks per CU
   c.col_wpb = (static_cast<int64_t>(wc) * (d.M / 8) >= 2 * 8192) ? 2 : 1;
+  const int64_t hs = d.M / 2 + 1;
+  c.htab = d.htab ? d.htab + static_cast<int64_t>(d.zslot[layer]) * d.W * hs * hs : nullptr;
   return c;
 }
 
+// algorithmic bytes of a column launch: staged rows in and kept rows out, plus every entry of
+// the wavelengths' transfer tables once when the plan has them
 int64_t col_bytes(const Design& d, int wc, int in_lo, int in_hi, int out_lo, int out_hi) {
-  return static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo));
+  const int64_t hs = d.M / 2 + 1;
+  return static_cast<int64_t>(wc) * d.M * 8 * ((in_hi - in_lo) + (out_hi - out_lo)) +
+         (d.htab ? static_cast<int64_t>(wc) * hs * hs * 8 : 0);
 }
 
 double col_flops(const Design& d, int wc) {
@@ -592,10 +635,10 @@ struct ColItem {
 
 void add_col_position(dpx_plan* p, const std::vector<ColItem>& items, bool conj,
                       std::vector<GroupLaunch>& out, TaskBlob& blob) {
-  std::map<std::array<int, 3>, std::vector<ColItem>> by_key;
+  std::map<std::array<int, 4>, std::vector<ColItem>> by_key;
   for (const auto& it : items) {
     const Design& d = p->designs[it.design];
-    by_key[{d.M, d.pad, d.col_variant}].push_back(it);
+    by_key[{d.M, d.pad, d.col_variant, d.htab ? 1 : 0}].push_back(it);
   }
   for (const auto& kv : by_key) {
     std::vector<dpx::ColTask> tasks;
@@ -621,6 +664,7 @@ void add_col_position(dpx_plan* p, const std::vector<ColItem>& items, bool conj,
     proto.M = kv.first[0];
     proto.pad = kv.first[1];
     proto.variant = kv.first[2];
+    proto.table = kv.first[3] != 0;
     proto.conj = conj;
     proto.pass = conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD;
     add_group(out, proto, tasks, nb, al, by, ub, fl, blob);
@@ -774,7 +818,7 @@ dpx_status run_groups(dpx_plan* p, const std::vector<GroupLaunch>& launches, con
     hipError_t e = hipErrorInvalidValue;
     switch (L.kind) {
       case GK_ROW: e = dpx::launch_row_group(L.M, L.pad, L.mode, g, s); break;
-      case GK_COL: e = dpx::launch_col_group(L.M, L.pad, L.conj, L.variant, g, s); break;
+      case GK_COL: e = dpx::launch_col_group(L.M, L.pad, L.conj, L.variant, L.table, g, s); break;
       case GK_BIN: e = dpx::launch_bin_group(g, out_f, s); break;
       case GK_DH: e = dpx::launch_dh_group(g, out_f, s); break;
       case GK_LOSS: break;
@@ -946,7 +990,7 @@ void dpx_opts_default(dpx_opts* o) {
   o->use_graph = 0;
   o->autotune = 0;
   o->force_variant = -1;
-  o->check_finite = 0;
+  o->transfer_table = 0;
   o->max_workspace_bytes = 0;
 }
 
@@ -1049,11 +1093,25 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     if ((st = dev_alloc(&d.ofov, static_cast<int64_t>(ck_w) * d.F * d.F * 8, "output field")) != DPX_OK) break;
     if ((st = dev_alloc(&d.dh_part, static_cast<int64_t>(d.nslots) * d.K * nn * 4, "gradient partials")) != DPX_OK) break;
     if ((st = dev_alloc(&d.per_wl, d.W * 8, "per-wavelength loss")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.htab, d.table_bytes, "transfer tables")) != DPX_OK) break;
     if (hipMemcpy(d.d_wl, tab.data(), d.W * sizeof(WlConst), hipMemcpyHostToDevice) != hipSuccess) {
       st = fail(DPX_E_DEVICE, "copy of the wavelength table failed");
       break;
     }
     p->bytes += d.bytes;
+    for (int k = 0; k < d.nzslots && st == DPX_OK; ++k) {
+      int l = 0;
+      while (d.zslot[l] != k) ++l;
+      const int64_t hs = d.M / 2 + 1;
+      const hipError_t e = dpx::launch_transfer_table(d.M, d.d_wl, d.W, d.z[l] / (static_cast<double>(d.M) * d.dx),
+                                                      d.htab + static_cast<int64_t>(k) * d.W * hs * hs, nullptr);
+      if (e != hipSuccess) st = fail(DPX_E_DEVICE, "transfer table launch failed: %s", hipGetErrorString(e));
+    }
+    if (st != DPX_OK) break;
+    if (d.nzslots > 0 && hipDeviceSynchronize() != hipSuccess) {
+      st = fail(DPX_E_DEVICE, "transfer table build failed");
+      break;
+    }
     if (!p->twiddles.count(d.M)) {
       std::vector<float2> tw;
       dpx::build_twiddle_table(d.M, tw);
@@ -1199,6 +1257,8 @@ dpx_status dpx_plan_layout(const dpx_plan* p, int32_t i, dpx_layout* out) {
   out->transform_len = d.M;
   out->target_side = d.T;
   out->workspace_bytes = d.bytes;
+  out->transfer_tables = d.nzslots;
+  out->reserved = 0;
   return ok();
 }
 

@@ -28,6 +28,10 @@ enum RowMode : int {
   ROW_ADJ_LAST = 5,   // row IFFT -> crop -> dL/dh_0 partial
 };
 
+// Threads per row-pass block: 512 (eight transforms of 1024) where the registers allow two
+// such blocks per CU next to their LDS, 256 for the register-heavy adjoint middle pass.
+constexpr int row_threads_of_mode(int mode) { return mode == ROW_ADJ_MID ? 256 : 512; }
+
 struct RowArgs {
   float2* spec;              // [wc][N][M] row-transformed planes of the current chunk
   const float* h;            // [N][N] heights of the layer used by this pass
@@ -60,6 +64,8 @@ struct ColArgs {
   int w_count;               // wavelengths in this launch
   int col_wpb;               // wavelengths each block runs (>= 1)
   const float2* dft;         // DFT matrices of the transform (matrix-core variant only)
+  const float2* htab;        // [W][M/2+1][M/2+1] H(|kx|, |ky|) / M^2 of this gap, or null:
+                             // evaluate H in the kernel (global w)
 };
 
 // ------------------------------------------------------------------------------------------
@@ -119,8 +125,35 @@ struct DhTask {
 
 constexpr int kGroupThreads = 256;  // threads per block of the grouped binning / reduction
 
+// Task of a grouped launch that block b belongs to: the last task whose first block is <= b
+// (the table of first blocks is a kernel argument, so the search runs on scalar loads).
+__device__ __forceinline__ int group_task(const GroupArgs& g, int b) {
+  int lo = 0, hi = g.ntasks;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (g.block0[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Supported transform lengths; the pass launchers of each live in their own translation unit.
+#define DPX_FOR_EACH_M(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
+#define DPX_DECLARE_PASS_LAUNCHERS(m)                                                                   \
+  hipError_t launch_row_##m(int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,       \
+                            hipStream_t s);                                                             \
+  hipError_t launch_row_group_##m(int pad, int mode, const GroupArgs& g, hipStream_t s);                \
+  hipError_t launch_col_##m(int pad, bool conj, int variant, const ColArgs& a, int w_count, hipStream_t s); \
+  hipError_t launch_col_group_##m(int pad, bool conj, int variant, bool table, const GroupArgs& g,       \
+                                  hipStream_t s);                                                       \
+  hipError_t launch_transfer_table_##m(const WlConst* wl, int W, double zrev, float2* out, hipStream_t s);
+DPX_FOR_EACH_M(DPX_DECLARE_PASS_LAUNCHERS)
+#undef DPX_DECLARE_PASS_LAUNCHERS
+
 hipError_t launch_row_group(int M, int pad, int mode, const GroupArgs& g, hipStream_t s);
-hipError_t launch_col_group(int M, int pad, bool conj, int variant, const GroupArgs& g, hipStream_t s);
+// table: every task's arguments carry a transfer table (else none does)
+hipError_t launch_col_group(int M, int pad, bool conj, int variant, bool table, const GroupArgs& g,
+                            hipStream_t s);
 hipError_t launch_bin_group(const GroupArgs& g, float* out, hipStream_t s);
 hipError_t launch_loss_group(const GroupArgs& g, const float* I, const float* tau, float* dl_di,
                              hipStream_t s);
@@ -140,6 +173,9 @@ extern const char* const kColVariantNames[kColVariants];
 int default_col_variant(int M);
 hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
                       hipStream_t s);
+// fills out[w][|kx|][|ky|] (w < W, |kx|, |ky| <= M/2) with H / M^2 of the gap z = zrev M dx,
+// by the same device function the column pass evaluates
+hipError_t launch_transfer_table(int M, const WlConst* wl, int W, double zrev, float2* out, hipStream_t s);
 hipError_t launch_bin_intensity(const float2* ofov, float* out, int w_count, int fov, int bin,
                                 hipStream_t s);
 hipError_t launch_loss(const float* I, const float* tau, float* dl_di, double* per_wl, int W, int T,

@@ -1,0 +1,163 @@
+// Launchers of the propagation passes for one transform length M = DPX_M: row passes (every
+// mode, single-design and grouped), column passes (every variant and transfer-function
+// source, single-design and grouped, and the matrix-core form) and the transfer table.  The
+// build compiles this file once per supported length, so the kernel templates of the
+// different lengths are instantiated in parallel translation units.
+#include "pass_kernels.hpp"
+
+#ifndef DPX_M
+#error "compile with -DDPX_M=<transform length>"
+#endif
+
+#define DPX_PASTE2(a, b) a##b
+#define DPX_PASTE(a, b) DPX_PASTE2(a, b)
+#define DPX_NAME(f) DPX_PASTE(f, DPX_M)
+
+namespace dpx {
+namespace {
+
+constexpr int M = DPX_M;
+
+unsigned group_grid(const GroupArgs& g) { return static_cast<unsigned>(g.block0[g.ntasks]); }
+
+template <int PAD>
+hipError_t row_mode(int mode, const RowArgs& a, dim3 grid, hipStream_t s) {
+  switch (mode) {
+#define DPX_ROW(MD) \
+  case MD: row_kernel<M, PAD, MD><<<grid, row_block_threads<M, MD>(), 0, s>>>(a); break;
+    DPX_ROW(ROW_FWD_FIRST)
+    DPX_ROW(ROW_FWD_MID)
+    DPX_ROW(ROW_FWD_LAST)
+    DPX_ROW(ROW_ADJ_SEED)
+    DPX_ROW(ROW_ADJ_MID)
+    DPX_ROW(ROW_ADJ_LAST)
+#undef DPX_ROW
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PAD>
+hipError_t row_group_mode(int mode, const GroupArgs& g, hipStream_t s) {
+  switch (mode) {
+#define DPX_ROW(MD) \
+  case MD: row_group_kernel<M, PAD, MD><<<group_grid(g), row_block_threads<M, MD>(), 0, s>>>(g); break;
+    DPX_ROW(ROW_FWD_FIRST)
+    DPX_ROW(ROW_FWD_MID)
+    DPX_ROW(ROW_FWD_LAST)
+    DPX_ROW(ROW_ADJ_SEED)
+    DPX_ROW(ROW_ADJ_MID)
+    DPX_ROW(ROW_ADJ_LAST)
+#undef DPX_ROW
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// H source of a launch: the table when the arguments carry one, else the variant's evaluation
+int h_mode(int variant, bool table) { return table ? kHTable : (variant >= 2 ? kHMirror : kHEval); }
+
+template <int PAD, int TX, int HM>
+hipError_t col_launch(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
+  dim3 grid(M / TX, (w_count + a.col_wpb - 1) / a.col_wpb);
+  if (conj)
+    col_kernel<M, PAD, true, TX, HM><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+  else
+    col_kernel<M, PAD, false, TX, HM><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int PAD, int TX>
+hipError_t col_launch_h(int hm, bool conj, const ColArgs& a, int w_count, hipStream_t s) {
+  if (hm == kHTable) return col_launch<PAD, TX, kHTable>(conj, a, w_count, s);
+  if (hm == kHMirror) return col_launch<PAD, TX, kHMirror>(conj, a, w_count, s);
+  return col_launch<PAD, TX, kHEval>(conj, a, w_count, s);
+}
+
+template <int PAD>
+hipError_t col_variant(int variant, bool conj, const ColArgs& a, int w_count, hipStream_t s) {
+  const int hm = h_mode(variant, a.htab != nullptr);
+  if (col_tile_width(M, variant) == 8) return col_launch_h<PAD, 8>(hm, conj, a, w_count, s);
+  return col_launch_h<PAD, 16>(hm, conj, a, w_count, s);
+}
+
+template <int PAD>
+hipError_t colgemm_launch(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
+  if constexpr (M <= 512 && M % 16 == 0 && (M / PAD) % 16 == 0) {
+    ColArgs one = a;
+    one.col_wpb = 1;
+    dim3 grid(M / kGemmTile, w_count);
+    if (conj)
+      colgemm_kernel<M, PAD, true><<<grid, gemm_threads(M), 0, s>>>(one, a.dft);
+    else
+      colgemm_kernel<M, PAD, false><<<grid, gemm_threads(M), 0, s>>>(one, a.dft);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int PAD, int TX, int HM>
+hipError_t col_group_tx(bool conj, const GroupArgs& g, hipStream_t s) {
+  if (conj)
+    col_group_kernel<M, PAD, true, TX, HM><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+  else
+    col_group_kernel<M, PAD, false, TX, HM><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+template <int PAD, int TX>
+hipError_t col_group_h(int hm, bool conj, const GroupArgs& g, hipStream_t s) {
+  if (hm == kHTable) return col_group_tx<PAD, TX, kHTable>(conj, g, s);
+  if (hm == kHMirror) return col_group_tx<PAD, TX, kHMirror>(conj, g, s);
+  return col_group_tx<PAD, TX, kHEval>(conj, g, s);
+}
+
+template <int PAD>
+hipError_t col_group_variant(int variant, bool table, bool conj, const GroupArgs& g, hipStream_t s) {
+  const int hm = h_mode(variant, table);
+  if (col_tile_width(M, variant) == 8) return col_group_h<PAD, 8>(hm, conj, g, s);
+  return col_group_h<PAD, 16>(hm, conj, g, s);
+}
+
+}  // namespace
+
+hipError_t DPX_NAME(launch_row_)(int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,
+                                 hipStream_t s) {
+  const dim3 grid(n_row_blocks, n_w_blocks);
+  if (pad == 2) return row_mode<2>(mode, a, grid, s);
+  if (pad == 1) return row_mode<1>(mode, a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t DPX_NAME(launch_row_group_)(int pad, int mode, const GroupArgs& g, hipStream_t s) {
+  if (pad == 2) return row_group_mode<2>(mode, g, s);
+  if (pad == 1) return row_group_mode<1>(mode, g, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t DPX_NAME(launch_col_)(int pad, bool conj, int variant, const ColArgs& a, int w_count, hipStream_t s) {
+  if (variant == 4) {
+    if (pad == 2) return colgemm_launch<2>(conj, a, w_count, s);
+    if (pad == 1) return colgemm_launch<1>(conj, a, w_count, s);
+    return hipErrorInvalidValue;
+  }
+  if (pad == 2) return col_variant<2>(variant, conj, a, w_count, s);
+  if (pad == 1) return col_variant<1>(variant, conj, a, w_count, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t DPX_NAME(launch_col_group_)(int pad, bool conj, int variant, bool table, const GroupArgs& g,
+                                       hipStream_t s) {
+  if (pad == 2) return col_group_variant<2>(variant, table, conj, g, s);
+  if (pad == 1) return col_group_variant<1>(variant, table, conj, g, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t DPX_NAME(launch_transfer_table_)(const WlConst* wl, int W, double zrev, float2* out, hipStream_t s) {
+  const dim3 grid(M / 2 + 1, W);
+  transfer_table_kernel<M><<<grid, 256, 0, s>>>(wl, zrev, out);
+  return hipGetLastError();
+}
+
+}  // namespace dpx

@@ -32,7 +32,7 @@ class CDesign(ctypes.Structure):
 class COpts(ctypes.Structure):
     _fields_ = [("checkpoint_mode", ctypes.c_int32), ("wl_chunk", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("force_variant", ctypes.c_int32), ("check_finite", ctypes.c_int32),
+                ("force_variant", ctypes.c_int32), ("transfer_table", ctypes.c_int32),
                 ("max_workspace_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("schedule", ctypes.c_int32)]
 
@@ -42,7 +42,8 @@ class CLayout(ctypes.Structure):
                 ("u_offset", ctypes.c_int64), ("u_count", ctypes.c_int64),
                 ("img_offset", ctypes.c_int64), ("img_count", ctypes.c_int64),
                 ("transform_len", ctypes.c_int32), ("target_side", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("transfer_tables", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class DpxError(RuntimeError):
@@ -126,7 +127,7 @@ def _c_designs(designs):
 
 
 def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
-          autotune=0, streams=0, use_graph=0, schedule=0):
+          autotune=0, streams=0, use_graph=0, schedule=0, transfer_table=0):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
@@ -137,6 +138,7 @@ def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_by
     o.use_graph = int(use_graph)
     o.max_workspace_bytes = max_workspace_bytes
     o.schedule = int(schedule)
+    o.transfer_table = int(transfer_table)
     return o
 
 
@@ -172,7 +174,8 @@ class Plan:
 
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
                  force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False,
-                 streams: int = 0, use_graph: bool = False, schedule: int = 0):
+                 streams: int = 0, use_graph: bool = False, schedule: int = 0,
+                 transfer_table: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
@@ -180,7 +183,7 @@ class Plan:
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
         o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune,
-                  streams, use_graph, schedule)
+                  streams, use_graph, schedule, transfer_table)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))
@@ -207,6 +210,10 @@ class Plan:
         v = ctypes.c_int32()
         _check(self.lib, self.lib.dpx_plan_variant(self._h, i, ctypes.byref(v)))
         return v.value
+
+    def has_transfer_tables(self) -> bool:
+        """Whether any design reads precomputed transfer-function tables."""
+        return any(lo["transfer_tables"] > 0 for lo in self.layouts)
 
     def schedule(self) -> int:
         """1: one launch per design and pass; 2: grouped launches over designs."""

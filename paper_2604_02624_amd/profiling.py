@@ -20,7 +20,8 @@ import sys
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_2604_02624_amd/csrc/dpx_kernels.hip", "paper_2604_02624_amd/csrc/fft.hpp",
+KERNEL_SOURCES = ["paper_2604_02624_amd/csrc/pass_kernels.hpp", "paper_2604_02624_amd/csrc/dpx_pass.hip",
+                  "paper_2604_02624_amd/csrc/dpx_kernels.hip", "paper_2604_02624_amd/csrc/fft.hpp",
                   "paper_2604_02624_amd/csrc/phase.hpp"]
 
 

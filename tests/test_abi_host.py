@@ -66,6 +66,18 @@ def test_query_store_vs_recompute_memory(lib):
     assert store - two >= 8 * 2 ** 30       # instead of 16 GiB for the whole workload at once
 
 
+def test_query_counts_transfer_tables(lib):
+    d = wk.make_workload(1)["designs"][0]           # N 64, M 128, 2 layers with one gap length
+    off = _query([d], transfer_table=1)
+    on = _query([d], transfer_table=2)
+    assert on - off == 1 * d["n_wl"] * 65 * 65 * 8
+    d2 = dict(d)
+    d2["z"] = np.array([d["z"][0], 2 * d["z"][0]])   # two gap lengths: two tables
+    assert _query([d2], transfer_table=2) - _query([d2], transfer_table=1) == 2 * d["n_wl"] * 65 * 65 * 8
+    with pytest.raises(dpx.DpxError):
+        _query([d], transfer_table=3)
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("n", 63, dpx.DPX_E_ARG),
     ("n", 0, dpx.DPX_E_ARG),

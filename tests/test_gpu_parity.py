@@ -434,6 +434,25 @@ def test_grouped_schedule_mixed_designs(torch_dev):
     assert per_wl_rel(Is[i].numpy(), I_ref).max() <= INT_TOL
 
 
+def test_transfer_tables_match_evaluation(torch_dev):
+    say("transfer tables vs H evaluated in the column pass: variants, several gaps, schedules")
+    ds, hs, us, taus = _mixed_designs(np.random.default_rng(91))
+    ref = run_gpu(torch_dev, ds, hs, taus, u_ins=us, schedule=1, streams=1, transfer_table=1)
+    for kw in (dict(schedule=1, streams=1, transfer_table=2), dict(transfer_table=2),
+               dict(transfer_table=2, force_variant=0), dict(transfer_table=2, force_variant=1)):
+        r = run_gpu(torch_dev, ds, hs, taus, u_ins=us, **kw)
+        assert torch_dev.equal(r["I"], ref["I"]), kw
+        assert torch_dev.equal(r["dh"], ref["dh"]), kw
+    # one design of a single gap length
+    w = wk.make_workload(3)
+    d = wk.subset_wavelengths(w["designs"][0], np.arange(0, 256, 16))
+    tau = w["targets"][0][::16]
+    a = run_gpu(torch_dev, [d], [w["h"][0]], [tau], transfer_table=1)
+    b = run_gpu(torch_dev, [d], [w["h"][0]], [tau], transfer_table=2)
+    assert b["plan"].has_transfer_tables() and not a["plan"].has_transfer_tables()
+    assert torch_dev.equal(a["I"], b["I"]) and torch_dev.equal(a["dh"], b["dh"])
+
+
 def test_grouped_schedule_splits_large_groups(torch_dev):
     say("grouped schedule: 70 designs of one transform length (two launches per pass)")
     rng = np.random.default_rng(70)
