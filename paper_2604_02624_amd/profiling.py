@@ -9,6 +9,8 @@
     python -m paper_2604_02624_amd.profiling stats <kernel_stats.csv> <command...>
     python -m paper_2604_02624_amd.profiling traffic <fetch.csv> <write.csv> <copy_mib> \\
         <kernel substring> <pass name> <command...>
+    python -m paper_2604_02624_amd.profiling counters <A.csv> <B.csv> <fetch.csv> <write.csv> \\
+        <copy_mib> <kernel substring> <command...>
 """
 from __future__ import annotations
 
@@ -81,9 +83,68 @@ def traffic_record(fetch_csv: str, write_csv: str, copy_mib: int, kernel_sub: st
     )
 
 
+def _dispatch_counters(csv_path: str):
+    """{dispatch: {counter: summed value, "_kernel": name, "_ns": duration}}"""
+    out = defaultdict(lambda: defaultdict(float))
+    for r in csv.DictReader(open(csv_path)):
+        d = out[int(r["Dispatch_Id"])]
+        d[r["Counter_Name"]] += float(r["Counter_Value"])
+        d["_kernel"] = r["Kernel_Name"]
+        d["_ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    return out
+
+
+def counters_markdown(a_csv: str, b_csv: str, fetch_csv: str, write_csv: str, copy_mib: int,
+                      kernel_filter: str, command: str, n_cu: int = 256, n_xcd: int = 8) -> str:
+    """Per-kernel table from four counter passes over the same program: A (SQ_WAVES
+    SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_INST_LDS
+    SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE GRBM_GUI_ACTIVE), B (SQ_INSTS_LDS SQ_WAIT_ANY ...),
+    FETCH_SIZE and WRITE_SIZE.  Averages over the dispatches of each kernel."""
+    A, B = _dispatch_counters(a_csv), _dispatch_counters(b_csv)
+    F, W = _dispatch_counters(fetch_csv), _dispatch_counters(write_csv)
+    copy_bytes = copy_mib * (1 << 20)
+
+    def copy_scale(rows, counter):
+        big = [d[counter] * 1024 for d in rows.values() if "copyBuffer" in d["_kernel"]]
+        return copy_bytes / max(big) if big else 1.0
+
+    fs, ws = copy_scale(F, "FETCH_SIZE"), copy_scale(W, "WRITE_SIZE")
+    per = defaultdict(list)
+    for k, a in A.items():
+        name = a["_kernel"]
+        if kernel_filter not in name:
+            continue
+        b = B.get(k, {})
+        cyc = a["GRBM_GUI_ACTIVE"] / n_xcd  # GRBM counts once per XCD
+        waves = max(a["SQ_WAVES"], 1.0)
+        per[name].append(dict(
+            ms=a["_ns"] / 1e6, clock=cyc / max(a["_ns"], 1) , valu=a["SQ_ACTIVE_INST_VALU"] / (n_cu * cyc),
+            vi=a["SQ_INSTS_VALU"] / waves, li=b.get("SQ_INSTS_LDS", 0.0) / waves,
+            vm=b.get("SQ_INSTS_VMEM_RD", 0.0) / waves,
+            wait=b.get("SQ_WAIT_ANY", 0.0) / max(a["SQ_WAVE_CYCLES"], 1.0),
+            conf=a["SQ_LDS_BANK_CONFLICT"] / max(a["SQ_LDS_IDX_ACTIVE"], 1.0),
+            rd=F.get(k, {}).get("FETCH_SIZE", 0.0) * 1024 * fs / 1e9,
+            wr=W.get(k, {}).get("WRITE_SIZE", 0.0) * 1024 * ws / 1e9))
+    rows = ["| kernel | launches | ms | clock GHz | VALU busy | VALU instr / wave | LDS instr / wave | "
+            "VMEM rd / wave | wave time waiting | LDS conflict cycles | HBM read GB | HBM write GB |",
+            "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, v in sorted(per.items(), key=lambda kv: -sum(x["ms"] for x in kv[1])):
+        m = {key: sum(x[key] for x in v) / len(v) for key in v[0]}
+        rows.append(f"| `{name[:60]}` | {len(v)} | {m['ms']:.2f} | {m['clock']:.2f} | {100 * m['valu']:.0f}% | "
+                    f"{m['vi']:.0f} | {m['li']:.0f} | {m['vm']:.0f} | {100 * m['wait']:.0f}% | "
+                    f"{100 * m['conf']:.0f}% | {m['rd']:.2f} | {m['wr']:.2f} |")
+    note = (f"VALU busy = SQ_ACTIVE_INST_VALU / ({n_cu} CUs x GRBM_GUI_ACTIVE / {n_xcd} XCDs); clock = "
+            f"GRBM_GUI_ACTIVE / {n_xcd} / duration; wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES; LDS conflict = "
+            f"SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.  HBM bytes: FETCH_SIZE x {fs:.2f} and WRITE_SIZE x "
+            f"{ws:.2f} (a {copy_mib} MiB device copy in the same process calibrates both).")
+    return "\n".join([f"Command (four passes): `{command}`", "", note, "", *rows, ""])
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats_markdown(argv[1], " ".join(argv[2:])))
+    elif argv[0] == "counters":
+        print(counters_markdown(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6], " ".join(argv[7:])))
     elif argv[0] == "traffic":
         rec = traffic_record(argv[1], argv[2], int(argv[3]), argv[4], argv[5], " ".join(argv[6:]))
         print(json.dumps(rec, indent=1))
