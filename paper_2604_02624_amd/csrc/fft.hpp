@@ -305,9 +305,9 @@ struct Plan;
 template <> struct Plan<64>   { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {16, 4, 0, 0}; };
 template <> struct Plan<96>   { static constexpr int E = 24, NST = 3, SH = 6, RX = 1, CX = 1;  static constexpr int R[4] = {3, 8, 4, 0}; };
 template <> struct Plan<128>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {16, 8, 0, 0}; };
-template <> struct Plan<192>  { static constexpr int E = 24, NST = 3, SH = 3, RX = 4, CX = 4;  static constexpr int R[4] = {3, 8, 8, 0}; };
+template <> struct Plan<192>  { static constexpr int E = 12, NST = 3, SH = 3, RX = 0, CX = 0;  static constexpr int R[4] = {12, 4, 4, 0}; };
 template <> struct Plan<256>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 8;  static constexpr int R[4] = {16, 16, 0, 0}; };
-template <> struct Plan<384>  { static constexpr int E = 24, NST = 3, SH = 3, RX = 8, CX = 8;  static constexpr int R[4] = {6, 8, 8, 0}; };
+template <> struct Plan<384>  { static constexpr int E = 12, NST = 4, SH = 5, RX = 4, CX = 0;  static constexpr int R[4] = {12, 4, 4, 2}; };
 template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX = 16, CX = 16; static constexpr int R[4] = {8, 8, 8, 0}; };
 template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 5, RX = 0, CX = 4;  static constexpr int R[4] = {16, 16, 4, 0}; };
 
