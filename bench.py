@@ -12,7 +12,9 @@ checkpoints.  Inputs are seeded synthetic arrays (paper_2604_02624_amd.workloads
 Printed: one JSON line with the throughput, the live roofline of the dominant kernel (HIP
 events around each of its launches inside the timed region, algorithmic bytes per launch),
 the FP64 CPU oracle timed on a bounded sample of the same workload, and a plain per-wavelength
-torch FFT loop (rocFFT + autograd) timed on a sample of wavelengths on the same GPU.
+torch FFT loop (rocFFT + autograd) timed on a sample of wavelengths on the same GPU.  After the
+timed region: the median / p10 / p90 of single steps, a forward-only rate, and this GPU's
+device-copy bandwidth (context for the HBM fractions).
 """
 import argparse
 import hashlib
@@ -137,6 +139,8 @@ def main():
     ap.add_argument("--streams", type=int, default=0, help="concurrent chunk lanes (0 automatic)")
     ap.add_argument("--transfer-table", type=int, default=0, choices=[0, 1, 2],
                     help="transfer-function tables: 0 automatic, 1 never, 2 always")
+    ap.add_argument("--small-path", type=int, default=0, choices=[0, 1],
+                    help="short transforms: 0 LDS-resident launches where supported, 1 multi-pass")
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
                     help="several designs: 0 automatic, 1 per design, 2 grouped launches")
     ap.add_argument("--graph", action="store_true",
@@ -144,6 +148,9 @@ def main():
                          "direct step after the timed region)")
     ap.add_argument("--variant", type=int, default=-1, help="column-pass variant (-1 automatic)")
     ap.add_argument("--autotune", action="store_true", help="time column-pass variants at plan creation")
+    ap.add_argument("--reps", type=int, default=10,
+                    help="single steps and forward calls timed one by one after the timed region "
+                         "(median, p10, p90); 0 skips them")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -170,7 +177,8 @@ def main():
     designs = w["designs"]
     plan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
                     force_variant=args.variant, autotune=args.autotune, streams=args.streams,
-                    use_graph=args.graph, schedule=args.schedule, transfer_table=args.transfer_table)
+                    use_graph=args.graph, schedule=args.schedule, transfer_table=args.transfer_table,
+                    small_path=args.small_path)
     variant = dpx.variant_names()[plan.variant(0)]
     log(f"[bench] column-pass variant {variant}")
     h = plan.pack_heights(w["h"])
@@ -253,6 +261,33 @@ def main():
                     for k, v in passes.items() if v["launches"]}
     all_bytes = sum(v["bytes"] for v in passes.values())
     step_gbs = all_bytes / args.steps / (ms_step / 1e3) / 1e9
+
+    # after the timed region: the spread of single steps, a forward-only rate, and the device
+    # copy bandwidth of this GPU as context for the HBM fractions
+    extra = {}
+    if args.reps > 0:
+        def timed(fn):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1)
+        steps_ms = sorted(timed(step) for _ in range(args.reps))
+        fwd_ms = sorted(timed(lambda: plan.forward(h, None, I)) for _ in range(args.reps))
+        pick = lambda v, q: v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+        extra["step_ms"] = dict(median=round(pick(steps_ms, 0.5), 3), p10=round(pick(steps_ms, 0.1), 3),
+                                p90=round(pick(steps_ms, 0.9), 3), reps=args.reps)
+        extra["forward_only"] = dict(value=round(props / (pick(fwd_ms, 0.5) / 1e3), 1),
+                                     unit="propagations/s (forward)", ms_median=round(pick(fwd_ms, 0.5), 3))
+        n = (1 << 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        cms = sorted(timed(lambda: dst.copy_(src)) for _ in range(5))
+        extra["device_copy_gbs"] = round(2 * (1 << 30) / (pick(cms, 0.5) / 1e3) / 1e9, 1)
+        del src, dst
+        log(f"[bench] spread of {args.reps} steps, forward-only and copy bandwidth done")
     # sanity: the loss is finite
     Lh = L.cpu().numpy()
     if not np.isfinite(Lh).all():
@@ -283,13 +318,14 @@ def main():
                     transform=d0["n"] * d0["pad"], checkpoint_mode=args.checkpoint_mode,
                     wl_chunk=args.wl_chunk, streams=args.streams, graph=args.graph,
                     schedule={1: "per-design", 2: "grouped"}[plan.schedule()],
-                    transfer_tables=plan.has_transfer_tables(),
+                    transfer_tables=plan.has_transfer_tables(), lds_resident=plan.uses_lds_path(),
                     column_variant=variant,
                     phase_args="f64"),
         roofline=roofline, cpu_baseline=cpu, plain_loop=plain,
         vs_plain_loop=(round(value / plain["value"], 2) if plain else None),
         passes=pass_summary, step_hbm=dict(achieved=round(step_gbs, 1), peak=HBM_PEAK_GBS,
                                            unit="GB/s", frac=round(step_gbs / HBM_PEAK_GBS, 4)),
+        **extra,
         wall_s=round(wall, 3),
     )
     print(json.dumps(out), flush=True)

@@ -138,6 +138,13 @@ typedef struct dpx_opts {
                                every design in one wavelength chunk on one stream and a
                                transform column variant (0-3), else DPX_E_UNSUPPORTED.
                                Results are bitwise identical across schedules. */
+  int32_t small_path;       /* transform lengths up to 128 (pad 2; up to 96 with pad 1) in
+                               store mode, per-design schedule, one stream, no forced column
+                               variant and no transfer tables: 0 = each
+                               wavelength's plane stays in LDS and the forward (with the
+                               binning) and the adjoint (with the dL/dh partials) are one launch
+                               each; 1 = the multi-pass kernels.  Same bits either way. */
+  int32_t reserved;
 } dpx_opts;
 
 /* Offsets (in elements of the buffer's type) of one design inside the packed buffers. */
@@ -150,7 +157,7 @@ typedef struct dpx_layout {
   int64_t workspace_bytes;         /* device bytes the plan holds for this design */
   int32_t transfer_tables;         /* transfer tables held for this design (one per distinct
                                       gap; 0 = H is evaluated in the column passes) */
-  int32_t reserved;
+  int32_t lds_path;                /* 1: this design runs LDS-resident (dpx_opts.small_path) */
 } dpx_layout;
 
 typedef struct dpx_plan dpx_plan;
@@ -214,7 +221,9 @@ typedef enum dpx_pass {
   DPX_PASS_ROW_ADJ_SEED = 5,  /* 2 dL/dI o -> row FFT */
   DPX_PASS_ROW_ADJ_MID = 6,   /* row IFFT -> dL/dh partial -> * conj(t_l) -> row FFT */
   DPX_PASS_ROW_ADJ_LAST = 7,  /* row IFFT -> dL/dh partial (first layer) */
-  DPX_PASS_COUNT = 8
+  DPX_PASS_LDS_FWD = 8,       /* LDS-resident forward of a whole design (short transforms) */
+  DPX_PASS_LDS_ADJ = 9,       /* LDS-resident adjoint of a whole design */
+  DPX_PASS_COUNT = 10
 } dpx_pass;
 
 /* Per-pass timers (measurement support).  While enabled, every launch of the passes above is

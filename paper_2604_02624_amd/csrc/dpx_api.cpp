@@ -62,6 +62,7 @@ struct Design {
   int nslots;        // lanes * slots_per_lane
   int row_group;     // rows per row-pass block
   int col_variant;   // column-pass kernel variant
+  bool lds = false;  // forward and adjoint as one LDS-resident launch each
   // transfer-function tables: one [W][M/2+1][M/2+1] table per distinct gap; zslot[l] is the
   // table of layer l's gap (empty: H is evaluated in the column pass)
   int nzslots = 0;
@@ -69,6 +70,7 @@ struct Design {
   int64_t table_bytes = 0;
   // device memory
   float2* htab = nullptr;
+  double* d_zrev = nullptr;  // [K] z_l / (M dx) (LDS-resident path)
   WlConst* d_wl = nullptr;
   float2* spec = nullptr;
   float2* ckpt = nullptr;
@@ -161,6 +163,7 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
     if (o->schedule < 0 || o->schedule > 2) return fail(DPX_E_ARG, "schedule must be 0, 1 or 2");
     if (o->transfer_table < 0 || o->transfer_table > 2)
       return fail(DPX_E_ARG, "transfer_table must be 0, 1 or 2");
+    if (o->small_path < 0 || o->small_path > 1) return fail(DPX_E_ARG, "small_path must be 0 or 1");
     if (o->max_workspace_bytes < 0) return fail(DPX_E_ARG, "max_workspace_bytes must be >= 0");
     if (o->force_variant < -1 || o->force_variant >= dpx::kColVariants)
       return fail(DPX_E_ARG, "force_variant must be -1 or a variant index below %d", dpx::kColVariants);
@@ -237,6 +240,14 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
     // chunks must hold whole blocks so every chunk maps onto the same partial slots
     chunk = std::max(wpb, chunk / wpb * wpb);
   }
+  // LDS-resident path for short transforms (opts.small_path): every wavelength is one block
+  // with one dL/dh slot, the whole design one chunk
+  d.lds = o.small_path != 1 && o.checkpoint_mode == 0 && o.streams <= 1 && o.force_variant < 0 &&
+          o.transfer_table != 2 && dpx::lds_path_supported(d.M, d.pad);
+  if (d.lds) {
+    chunk = d.W;
+    wpb = 1;
+  }
   d.wl_chunk = chunk;
   d.nchunks = (d.W + chunk - 1) / chunk;
   d.lanes = std::max(1, std::min(lanes_wanted, d.nchunks));
@@ -270,7 +281,8 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
             + static_cast<int64_t>(of_w) * d.F * d.F * 8      // output field
             + static_cast<int64_t>(d.nslots) * d.K * nn * 4   // dL/dh partials
             + static_cast<int64_t>(d.W) * 8                   // per-wavelength loss
-            + static_cast<int64_t>(d.W) * sizeof(WlConst);
+            + static_cast<int64_t>(d.W) * sizeof(WlConst)
+            + static_cast<int64_t>(d.K) * 8;                  // gap table
   const bool want = o.transfer_table == 2;
   if (want) {
     d.bytes += d.table_bytes;
@@ -289,7 +301,9 @@ void free_design(Design& d) {
   hipFree(d.dh_part);
   hipFree(d.per_wl);
   hipFree(d.htab);
+  hipFree(d.d_zrev);
   d.htab = nullptr;
+  d.d_zrev = nullptr;
   d.d_wl = nullptr;
   d.spec = d.ckpt = d.ofov = nullptr;
   d.dh_part = nullptr;
@@ -830,6 +844,48 @@ dpx_status run_groups(dpx_plan* p, const std::vector<GroupLaunch>& launches, con
   return DPX_OK;
 }
 
+// LDS-resident forward (with the intensity binning) or adjoint (with the dL/dh partials) of a
+// whole design in one launch
+dpx_status run_lds(dpx_plan* p, const Design& d, bool adjoint, const float* h, const float* u_in,
+                   float* intensity, const float* dl_di, hipStream_t s) {
+  dpx::LdsArgs a{};
+  a.wl = d.d_wl;
+  a.tw = p->twiddles.at(d.M);
+  a.zrev = d.d_zrev;
+  a.h = h + d.h_off;
+  a.u_in = u_in ? reinterpret_cast<const float2*>(u_in) + d.u_off : nullptr;
+  a.ckpt = d.ckpt;
+  a.ofov = d.ofov;
+  a.intensity = intensity ? intensity + d.img_off : nullptr;
+  a.dl_di = dl_di ? dl_di + d.img_off : nullptr;
+  a.dh_part = d.dh_part;
+  a.K = d.K;
+  a.fov = d.F;
+  a.bin = d.b;
+  a.W = d.W;
+  // algorithmic work: every pass of the multi-kernel path, without its spectrum traffic
+  const int fo = (d.N - d.F) / 2;
+  double flops = 0.0;
+  int64_t bytes = static_cast<int64_t>(d.K) * d.N * d.N * 4 + (u_in ? 8LL * d.N * d.N : 0);
+  const int64_t nn = static_cast<int64_t>(d.N) * d.N;
+  if (!adjoint) {
+    flops += row_flops(d, dpx::ROW_FWD_FIRST, d.W, d.N) + (d.K - 1) * row_flops(d, dpx::ROW_FWD_MID, d.W, d.N) +
+             row_flops(d, dpx::ROW_FWD_LAST, d.W, d.F) + d.K * col_flops(d, d.W);
+    bytes += static_cast<int64_t>(d.W) * (d.K * nn * 8 + d.F * d.F * 8 + d.T * d.T * 4);
+  } else {
+    flops += row_flops(d, dpx::ROW_ADJ_SEED, d.W, d.F) + (d.K - 1) * row_flops(d, dpx::ROW_ADJ_MID, d.W, d.N) +
+             row_flops(d, dpx::ROW_ADJ_LAST, d.W, d.N) + d.K * col_flops(d, d.W);
+    bytes += static_cast<int64_t>(d.W) * (d.K * nn * 8 + d.F * d.F * 8 + d.T * d.T * 4 + d.K * nn * 4);
+  }
+  (void)fo;
+  TimedLaunch t{adjoint ? DPX_PASS_LDS_ADJ : DPX_PASS_LDS_FWD, nullptr, nullptr, bytes, flops};
+  DPX_TRY(timer_begin(p, s, t));
+  hipError_t e = dpx::launch_lds(d.M, d.pad, adjoint, a, s);
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "LDS-resident pass launch failed: %s", hipGetErrorString(e));
+  DPX_TRY(timer_end(p, s, t));
+  return DPX_OK;
+}
+
 // Chunk c of a design runs on lane c % lanes.  Lane 0 is the caller's stream; the other
 // lanes fork from it, start one pass behind lane 0 (so that the column pass of one chunk
 // meets the row pass of another), and join back before the call returns.
@@ -991,6 +1047,7 @@ void dpx_opts_default(dpx_opts* o) {
   o->autotune = 0;
   o->force_variant = -1;
   o->transfer_table = 0;
+  o->small_path = 0;
   o->max_workspace_bytes = 0;
 }
 
@@ -1094,6 +1151,15 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     if ((st = dev_alloc(&d.dh_part, static_cast<int64_t>(d.nslots) * d.K * nn * 4, "gradient partials")) != DPX_OK) break;
     if ((st = dev_alloc(&d.per_wl, d.W * 8, "per-wavelength loss")) != DPX_OK) break;
     if ((st = dev_alloc(&d.htab, d.table_bytes, "transfer tables")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.d_zrev, static_cast<int64_t>(d.K) * 8, "gap table")) != DPX_OK) break;
+    {
+      std::vector<double> zr(d.K);
+      for (int l = 0; l < d.K; ++l) zr[l] = d.z[l] / (static_cast<double>(d.M) * d.dx);
+      if (hipMemcpy(d.d_zrev, zr.data(), d.K * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        st = fail(DPX_E_DEVICE, "copy of the gap table failed");
+        break;
+      }
+    }
     if (hipMemcpy(d.d_wl, tab.data(), d.W * sizeof(WlConst), hipMemcpyHostToDevice) != hipSuccess) {
       st = fail(DPX_E_DEVICE, "copy of the wavelength table failed");
       break;
@@ -1132,6 +1198,8 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
   const bool try_group = o.schedule == 2 || (o.schedule == 0 && nd > 1 && o.streams <= 1);
   if (st == DPX_OK && try_group) {
     p->grouped = groupable(p);
+    if (p->grouped)
+      for (auto& d : p->designs) d.lds = false;  // the grouped launches take every design
     if (!p->grouped && o.schedule == 2)
       st = fail(DPX_E_UNSUPPORTED,
                 "the grouped schedule needs checkpoint_mode 0, every design in one wavelength chunk "
@@ -1258,7 +1326,7 @@ dpx_status dpx_plan_layout(const dpx_plan* p, int32_t i, dpx_layout* out) {
   out->target_side = d.T;
   out->workspace_bytes = d.bytes;
   out->transfer_tables = d.nzslots;
-  out->reserved = 0;
+  out->lds_path = d.lds ? 1 : 0;
   return ok();
 }
 
@@ -1288,6 +1356,7 @@ dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* in
     if (p->grouped)
       return run_group_parts(p, p->g_fwd, {h, reinterpret_cast<const float2*>(u_in), nullptr}, intensity, s0);
     return for_each_design(p, s0, [&](const Design& d, int, hipStream_t s) -> dpx_status {
+      if (d.lds) return run_lds(p, d, false, h, u_in, intensity, nullptr, s);
       DPX_TRY(fork_lanes(p, d, s));
       for (int c = 0; c < d.nchunks; ++c) {
         const int lane = c % d.lanes;
@@ -1363,6 +1432,13 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
     if (p->grouped)
       return run_group_parts(p, p->g_bwd, {h, reinterpret_cast<const float2*>(u_in), dl_di}, dl_dh, s0);
     return for_each_design(p, s0, [&](const Design& d, int, hipStream_t s) -> dpx_status {
+      if (d.lds) {
+        DPX_TRY(run_lds(p, d, true, h, u_in, nullptr, dl_di, s));
+        hipError_t e = dpx::launch_dh_reduce(d.dh_part, dl_dh + d.h_off, d.nslots,
+                                             static_cast<int64_t>(d.K) * d.N * d.N, s);
+        if (e != hipSuccess) return fail(DPX_E_DEVICE, "gradient reduction launch failed: %s", hipGetErrorString(e));
+        return DPX_OK;
+      }
       DPX_TRY(fork_lanes(p, d, s));
       for (int c = 0; c < d.nchunks; ++c) {
         const int lane = c % d.lanes;

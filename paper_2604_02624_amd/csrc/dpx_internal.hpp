@@ -69,6 +69,50 @@ struct ColArgs {
 };
 
 // ------------------------------------------------------------------------------------------
+// LDS-resident path for short transforms (M <= 128): one block per wavelength keeps its plane
+// in LDS and runs every layer of the forward (with the intensity binning) or of the adjoint
+// (with the dL/dh partials) in one launch.
+// ------------------------------------------------------------------------------------------
+struct LdsArgs {
+  const WlConst* wl;         // [W]
+  const float2* tw;          // per-stage twiddle table of the transform length
+  const double* zrev;        // [K] z_l / (M dx)
+  const float* h;            // [K][N][N] heights of the design
+  const float2* u_in;        // [N][N] or null (unit plane wave)
+  float2* ckpt;              // [K][W][N][N] fields after each transmission
+  float2* ofov;              // [W][F][F] output field on the field of view
+  float* intensity;          // [W][T][T] (forward)
+  const float* dl_di;        // [W][T][T] (adjoint)
+  float* dh_part;            // [W][K][N][N] dL/dh of each wavelength (adjoint)
+  int K, fov, bin, W;
+};
+
+// Intensity of output i of a [w_count][T][T] image set: sum of |o|^2 over the b x b bin of the
+// [w_count][fov][fov] window field (fused multiply-adds in a fixed order)
+__device__ __forceinline__ void bin_intensity_body(const float2* __restrict__ ofov, float* __restrict__ out,
+                                                   int w_count, int fov, int bin, size_t i) {
+  const int T = fov / bin;
+  const size_t total = static_cast<size_t>(w_count) * T * T;
+  if (i >= total) return;
+  const int w = static_cast<int>(i / (static_cast<size_t>(T) * T));
+  const int r = static_cast<int>(i % (static_cast<size_t>(T) * T));
+  const int ty = r / T, tx = r % T;
+  const float2* o = ofov + static_cast<size_t>(w) * fov * fov;
+  float s = 0.f;
+  for (int a = 0; a < bin; ++a)
+    for (int b = 0; b < bin; ++b) {
+      const float2 v = o[static_cast<size_t>(ty * bin + a) * fov + tx * bin + b];
+      s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
+    }
+  out[i] = s;
+}
+
+constexpr int kLdsThreads = 512;
+// whether the LDS-resident kernels are built for this transform length and pad
+bool lds_path_supported(int M, int pad);
+hipError_t launch_lds(int M, int pad, bool adjoint, const LdsArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------------------------------------
 // Grouped launches: one launch of a pass for several designs that share the transform length
 // (and pad, mode, column variant).  Each design is a task owning a contiguous run of blocks
 // of a one-dimensional grid; the first block of every task travels in the kernel argument
@@ -146,7 +190,9 @@ __device__ __forceinline__ int group_task(const GroupArgs& g, int b) {
   hipError_t launch_col_##m(int pad, bool conj, int variant, const ColArgs& a, int w_count, hipStream_t s); \
   hipError_t launch_col_group_##m(int pad, bool conj, int variant, bool table, const GroupArgs& g,       \
                                   hipStream_t s);                                                       \
-  hipError_t launch_transfer_table_##m(const WlConst* wl, int W, double zrev, float2* out, hipStream_t s);
+  hipError_t launch_transfer_table_##m(const WlConst* wl, int W, double zrev, float2* out, hipStream_t s); \
+  hipError_t launch_lds_##m(int pad, bool adjoint, const LdsArgs& a, hipStream_t s);                     \
+  bool lds_supported_##m(int pad);
 DPX_FOR_EACH_M(DPX_DECLARE_PASS_LAUNCHERS)
 #undef DPX_DECLARE_PASS_LAUNCHERS
 

@@ -12,23 +12,6 @@ namespace dpx {
 // ------------------------------------------------------------------------------------------
 // Small kernels
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void bin_intensity_body(const float2* __restrict__ ofov, float* __restrict__ out,
-                                                   int w_count, int fov, int bin, size_t i) {
-  const int T = fov / bin;
-  const size_t total = static_cast<size_t>(w_count) * T * T;
-  if (i >= total) return;
-  const int w = static_cast<int>(i / (static_cast<size_t>(T) * T));
-  const int r = static_cast<int>(i % (static_cast<size_t>(T) * T));
-  const int ty = r / T, tx = r % T;
-  const float2* o = ofov + static_cast<size_t>(w) * fov * fov;
-  float s = 0.f;
-  for (int a = 0; a < bin; ++a)
-    for (int b = 0; b < bin; ++b) {
-      const float2 v = o[static_cast<size_t>(ty * bin + a) * fov + tx * bin + b];
-      s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
-    }
-  out[i] = s;
-}
 
 __global__ void bin_intensity_kernel(const float2* __restrict__ ofov, float* __restrict__ out,
                                      int w_count, int fov, int bin) {
@@ -301,6 +284,26 @@ hipError_t launch_col_group(int M, int pad, bool conj, int variant, bool table, 
   if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks || variant < 0 || variant > 3) return hipErrorInvalidValue;
   switch (M) {
 #define DPX_CASE(m) case m: return launch_col_group_##m(pad, conj, variant, table, g, s);
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+bool lds_path_supported(int M, int pad) {
+  switch (M) {
+#define DPX_CASE(m) case m: return lds_supported_##m(pad);
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default:
+      return false;
+  }
+}
+
+hipError_t launch_lds(int M, int pad, bool adjoint, const LdsArgs& a, hipStream_t s) {
+  switch (M) {
+#define DPX_CASE(m) case m: return launch_lds_##m(pad, adjoint, a, s);
     DPX_FOR_EACH_M(DPX_CASE)
 #undef DPX_CASE
     default:

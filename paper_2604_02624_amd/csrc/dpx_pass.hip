@@ -154,6 +154,30 @@ hipError_t DPX_NAME(launch_col_group_)(int pad, bool conj, int variant, bool tab
   return hipErrorInvalidValue;
 }
 
+bool DPX_NAME(lds_supported_)(int pad) {
+  return pad == 2 ? LdsGeo<M, 2>::FITS && M <= 128 : pad == 1 ? LdsGeo<M, 1>::FITS && M <= 128 : false;
+}
+
+hipError_t DPX_NAME(launch_lds_)(int pad, bool adjoint, const LdsArgs& a, hipStream_t s) {
+  if constexpr (M <= 128) {
+    auto go = [&](auto padc) -> hipError_t {
+      constexpr int PD = decltype(padc)::value;
+      if constexpr (LdsGeo<M, PD>::FITS) {
+        if (adjoint)
+          lds_adjoint_kernel<M, PD><<<a.W, kLdsThreads, 0, s>>>(a);
+        else
+          lds_forward_kernel<M, PD><<<a.W, kLdsThreads, 0, s>>>(a);
+        return hipGetLastError();
+      } else {
+        return hipErrorInvalidValue;
+      }
+    };
+    if (pad == 2) return go(std::integral_constant<int, 2>{});
+    if (pad == 1) return go(std::integral_constant<int, 1>{});
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t DPX_NAME(launch_transfer_table_)(const WlConst* wl, int W, double zrev, float2* out, hipStream_t s) {
   const dim3 grid(M / 2 + 1, W);
   transfer_table_kernel<M><<<grid, 256, 0, s>>>(wl, zrev, out);

@@ -571,4 +571,205 @@ __global__ void __launch_bounds__(gemm_threads(M)) colgemm_kernel(ColArgs a, con
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// LDS-resident path for short transforms.  A block owns one wavelength.  Its N aperture rows
+// live in LDS with a row stride equal to a row transform's exchange region, so every row
+// transforms in place; a batch of CB columns at a time gathers its column from the rows and
+// exchanges through regions of its own.  Every step is the one the multi-kernel path takes
+// (same transforms, transmission, transfer function, products, partial-sum order), so the
+// results are the same bits.
+// ------------------------------------------------------------------------------------------
+template <int M, int PAD>
+struct LdsGeo {
+  static constexpr int N = M / PAD;
+  static constexpr int P = Geo<M>::P;
+  static constexpr int RS = Geo<M>::ROW_REGION;               // row stride of the plane
+  static constexpr int CS = Geo<M>::COL_REGION;               // column exchange region
+  static constexpr int RB = kLdsThreads / P;                  // rows transformed at once
+  static constexpr int CB = RB < M ? RB : M;                  // columns transformed at once
+  static constexpr long long LDS_BYTES = 8LL * (static_cast<long long>(N) * RS + CB * CS + twiddle_count<M>());
+  static constexpr bool FITS = LDS_BYTES <= 160 * 1024;
+  // the forward's window field (F <= N) is staged in the column regions for the binning
+  static_assert(static_cast<long long>(CB) * CS >= static_cast<long long>(N) * N, "window staging");
+};
+
+// forward rows of one layer: FIRST = input field times t_0, else inverse row transform of the
+// plane row, crop, times t_layer; checkpoint; zero-padded forward row transform in place
+template <int M, int PAD, bool FIRST>
+__device__ __forceinline__ void lds_rows_forward(const LdsArgs& a, const WlConst& c, int w, int layer,
+                                                 float2* plane, const float2* tw) {
+  using G = LdsGeo<M, PAD>;
+  constexpr int E = Geo<M>::E, P = G::P, N = G::N, EN = E / PAD;
+  constexpr bool HALF = (PAD == 2);
+  const int g = threadIdx.x / P, j0 = threadIdx.x % P;
+  const size_t nn = static_cast<size_t>(N) * N;
+  for (int y = g; y < N; y += G::RB) {
+    float2* row = plane + y * G::RS;
+    const float* hrow = a.h + (static_cast<size_t>(layer) * N + y) * N;
+    float2 reg[E];
+    if constexpr (FIRST) {
+#pragma unroll
+      for (int t = 0; t < EN; ++t) {
+        const float2 u = a.u_in ? a.u_in[static_cast<size_t>(y) * N + j0 + P * t] : make_float2(1.f, 0.f);
+        reg[t] = cmul(u, transmission(hrow[j0 + P * t], c));
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
+      fft<M, true, false>(reg, row, j0, tw);
+#pragma unroll
+      for (int t = 0; t < EN; ++t) reg[t] = cmul(reg[t], transmission(hrow[j0 + P * t], c));
+    }
+    float2* ck = a.ckpt + (static_cast<size_t>(layer) * a.W + w) * nn + static_cast<size_t>(y) * N;
+#pragma unroll
+    for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
+    fft<M, false, HALF>(reg, row, j0, tw);
+#pragma unroll
+    for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
+  }
+}
+
+// column transforms of one gap: rows [in_lo, in_hi) in, H or conj(H), rows [0, N) back
+template <int M, int PAD, bool CONJ>
+__device__ __forceinline__ void lds_columns(const WlConst& c, double zrev, int in_lo, int in_hi,
+                                            float2* plane, float2* xch, const float2* tw) {
+  using G = LdsGeo<M, PAD>;
+  constexpr int E = Geo<M>::E, P = G::P, N = G::N, EN = E / PAD;
+  constexpr bool HALF = (PAD == 2);
+  const int g = threadIdx.x / P, j0 = threadIdx.x % P;
+  if (g >= G::CB) return;
+  float2* xr = xch + g * G::CS;
+  for (int kx = g; kx < M; kx += G::CB) {
+    float2 reg[E];
+#pragma unroll
+    for (int t = 0; t < EN; ++t) {
+      const int y = j0 + P * t;
+      reg[t] = (y >= in_lo && y < in_hi) ? plane[y * G::RS + kx] : make_float2(0.f, 0.f);
+    }
+    fft<M, false, HALF>(reg, xr, j0, tw);
+    const int kxs = kx < M / 2 ? kx : kx - M;
+    const double base = c.q0 - static_cast<double>(kxs * kxs);
+#pragma unroll
+    for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], transfer<M, CONJ>(zrev, base, j0 + P * t));
+    fft<M, true, false>(reg, xr, j0, tw);
+#pragma unroll
+    for (int t = 0; t < EN; ++t) plane[(j0 + P * t) * G::RS + kx] = reg[t];
+  }
+}
+
+template <int M, int PAD>
+__global__ void __launch_bounds__(kLdsThreads) lds_forward_kernel(LdsArgs a) {
+  using G = LdsGeo<M, PAD>;
+  constexpr int E = Geo<M>::E, P = G::P, N = G::N, EN = E / PAD;
+  __shared__ float2 plane[N * G::RS];
+  __shared__ float2 xch[G::CB * G::CS];
+  __shared__ float2 tw[twiddle_count<M>()];
+  stage_twiddles<M>(tw, a.tw, threadIdx.x, kLdsThreads);
+  __syncthreads();
+  const int w = blockIdx.x;
+  const WlConst c = a.wl[w];
+  lds_rows_forward<M, PAD, true>(a, c, w, 0, plane, tw);
+  __syncthreads();
+  for (int l = 0; l < a.K; ++l) {
+    lds_columns<M, PAD, false>(c, a.zrev[l], 0, N, plane, xch, tw);
+    __syncthreads();
+    if (l + 1 < a.K) {
+      lds_rows_forward<M, PAD, false>(a, c, w, l + 1, plane, tw);
+      __syncthreads();
+    }
+  }
+  // last inverse row transforms on the window rows: output field, and its intensity in bins
+  const int F = a.fov, x0 = (N - F) / 2, T = F / a.bin;
+  const int g = threadIdx.x / P, j0 = threadIdx.x % P;
+  float2* win = xch;  // the column regions are free now
+  for (int y = x0 + g; y < x0 + F; y += G::RB) {
+    float2* row = plane + y * G::RS;
+    float2 reg[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
+    fft<M, true, false>(reg, row, j0, tw);
+    float2* dst = a.ofov + static_cast<size_t>(w) * F * F + static_cast<size_t>(y - x0) * F;
+#pragma unroll
+    for (int t = 0; t < EN; ++t) {
+      const int x = j0 + P * t;
+      if (x >= x0 && x < x0 + F) {
+        dst[x - x0] = reg[t];
+        win[(y - x0) * F + x - x0] = reg[t];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < T * T; i += kLdsThreads)
+    bin_intensity_body(win, a.intensity + static_cast<size_t>(w) * T * T, 1, F, a.bin, i);
+}
+
+template <int M, int PAD>
+__global__ void __launch_bounds__(kLdsThreads) lds_adjoint_kernel(LdsArgs a) {
+  using G = LdsGeo<M, PAD>;
+  constexpr int E = Geo<M>::E, P = G::P, N = G::N, EN = E / PAD;
+  constexpr bool HALF = (PAD == 2);
+  __shared__ float2 plane[N * G::RS];
+  __shared__ float2 xch[G::CB * G::CS];
+  __shared__ float2 tw[twiddle_count<M>()];
+  stage_twiddles<M>(tw, a.tw, threadIdx.x, kLdsThreads);
+  __syncthreads();
+  const int w = blockIdx.x;
+  const WlConst c = a.wl[w];
+  const int F = a.fov, b = a.bin, T = F / b, x0 = (N - F) / 2;
+  const int g = threadIdx.x / P, j0 = threadIdx.x % P;
+  const size_t nn = static_cast<size_t>(N) * N;
+  // seed 2 (dL/dI) o on the window rows, forward row transform
+  for (int y = x0 + g; y < x0 + F; y += G::RB) {
+    float2* row = plane + y * G::RS;
+    const float2* o = a.ofov + static_cast<size_t>(w) * F * F + static_cast<size_t>(y - x0) * F;
+    const float* d = a.dl_di + static_cast<size_t>(w) * T * T + static_cast<size_t>((y - x0) / b) * T;
+    float2 reg[E];
+#pragma unroll
+    for (int t = 0; t < EN; ++t) {
+      const int x = j0 + P * t;
+      if (x >= x0 && x < x0 + F) {
+        const float s = 2.0f * d[(x - x0) / b];
+        reg[t] = cscale(o[x - x0], s);
+      } else {
+        reg[t] = make_float2(0.f, 0.f);
+      }
+    }
+    fft<M, false, HALF>(reg, row, j0, tw);
+#pragma unroll
+    for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
+  }
+  __syncthreads();
+  const float ct = static_cast<float>(c.ct), ca = static_cast<float>(c.ca);
+  for (int l = a.K - 1; l >= 0; --l) {
+    lds_columns<M, PAD, true>(c, a.zrev[l], l == a.K - 1 ? x0 : 0, l == a.K - 1 ? x0 + F : N, plane, xch, tw);
+    __syncthreads();
+    for (int y = g; y < N; y += G::RB) {
+      float2* row = plane + y * G::RS;
+      const float* hrow = a.h + (static_cast<size_t>(l) * N + y) * N;
+      const float2* ck = a.ckpt + (static_cast<size_t>(l) * a.W + w) * nn + static_cast<size_t>(y) * N;
+      float2 reg[E];
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
+      fft<M, true, false>(reg, row, j0, tw);
+      float* dst = a.dh_part + (static_cast<size_t>(w) * a.K + l) * nn + static_cast<size_t>(y) * N;
+#pragma unroll
+      for (int t = 0; t < EN; ++t) {
+        const float2 gv = reg[t];
+        const float2 v = ck[j0 + P * t];
+        // conj(g) v; -ct Im - ca Re
+        const float re = fmaf(gv.x, v.x, gv.y * v.y);
+        const float im = fmaf(gv.x, v.y, -(gv.y * v.x));
+        dst[j0 + P * t] = fmaf(-ct, im, fmaf(-ca, re, 0.f));
+        if (l > 0) reg[t] = cmulc(gv, transmission(hrow[j0 + P * t], c));
+      }
+      if (l > 0) {
+        fft<M, false, HALF>(reg, row, j0, tw);
+#pragma unroll
+        for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace dpx

@@ -34,7 +34,8 @@ class COpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("force_variant", ctypes.c_int32), ("transfer_table", ctypes.c_int32),
                 ("max_workspace_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("small_path", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CLayout(ctypes.Structure):
@@ -43,7 +44,7 @@ class CLayout(ctypes.Structure):
                 ("img_offset", ctypes.c_int64), ("img_count", ctypes.c_int64),
                 ("transform_len", ctypes.c_int32), ("target_side", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("transfer_tables", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lds_path", ctypes.c_int32)]
 
 
 class DpxError(RuntimeError):
@@ -127,7 +128,7 @@ def _c_designs(designs):
 
 
 def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
-          autotune=0, streams=0, use_graph=0, schedule=0, transfer_table=0):
+          autotune=0, streams=0, use_graph=0, schedule=0, transfer_table=0, small_path=0):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
@@ -139,6 +140,7 @@ def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_by
     o.max_workspace_bytes = max_workspace_bytes
     o.schedule = int(schedule)
     o.transfer_table = int(transfer_table)
+    o.small_path = int(small_path)
     return o
 
 
@@ -175,7 +177,7 @@ class Plan:
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
                  force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False,
                  streams: int = 0, use_graph: bool = False, schedule: int = 0,
-                 transfer_table: int = 0):
+                 transfer_table: int = 0, small_path: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
@@ -183,7 +185,7 @@ class Plan:
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
         o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune,
-                  streams, use_graph, schedule, transfer_table)
+                  streams, use_graph, schedule, transfer_table, small_path)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))
@@ -214,6 +216,10 @@ class Plan:
     def has_transfer_tables(self) -> bool:
         """Whether any design reads precomputed transfer-function tables."""
         return any(lo["transfer_tables"] > 0 for lo in self.layouts)
+
+    def uses_lds_path(self) -> bool:
+        """Whether any design runs as one LDS-resident launch per forward / adjoint."""
+        return any(lo["lds_path"] for lo in self.layouts)
 
     def schedule(self) -> int:
         """1: one launch per design and pass; 2: grouped launches over designs."""
@@ -287,7 +293,7 @@ class Plan:
 
     # -------------------------------------------------------------- per-pass timers
     PASS_NAMES = ["col_fwd", "col_adj", "row_fwd_first", "row_fwd_mid", "row_fwd_last",
-                  "row_adj_seed", "row_adj_mid", "row_adj_last"]
+                  "row_adj_seed", "row_adj_mid", "row_adj_last", "lds_fwd", "lds_adj"]
 
     def timing(self, enable: bool = True):
         _check(self.lib, self.lib.dpx_timing_enable(self._h, 1 if enable else 0))

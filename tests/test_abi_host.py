@@ -124,6 +124,8 @@ def test_query_rejects_bad_options(lib):
         _query([d], force_variant=5)
     with pytest.raises(dpx.DpxError):
         _query([d], schedule=3)
+    with pytest.raises(dpx.DpxError):
+        _query([d], small_path=2)
     assert _query([d], schedule=2) > 0
 
 

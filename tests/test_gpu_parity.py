@@ -453,6 +453,34 @@ def test_transfer_tables_match_evaluation(torch_dev):
     assert torch_dev.equal(a["I"], b["I"]) and torch_dev.equal(a["dh"], b["dh"])
 
 
+def test_lds_resident_path_matches_multi_pass(torch_dev):
+    say("LDS-resident forward / adjoint (one launch each) vs the multi-pass kernels")
+    w = wk.make_workload(2)
+    ref = run_gpu(torch_dev, w["designs"], w["h"], w["targets"], small_path=1)
+    lds = run_gpu(torch_dev, w["designs"], w["h"], w["targets"])
+    assert lds["plan"].uses_lds_path() and not ref["plan"].uses_lds_path()
+    for k in ("I", "L", "g", "dh"):
+        assert torch_dev.equal(lds[k], ref[k]), k
+    # every supported length and pad, input field, absorption, bins, one layer, one wavelength
+    rng = np.random.default_rng(8)
+    for n, pad, k, W, f, b in [(32, 2, 3, 5, 16, 2), (64, 1, 2, 3, 32, 1), (48, 2, 2, 4, 24, 3),
+                               (96, 1, 1, 2, 48, 2), (64, 2, 1, 1, 64, 1)]:
+        wl = np.linspace(480e-9, 700e-9, W)
+        d = wk.make_design(n=n, layers=k, wl=wl, n_mat=wk.cauchy_index(wl), dx=260e-9,
+                           z=list(np.linspace(6e-6, 11e-6, k)), fov=f, bin_=b, pad=pad,
+                           kappa=np.linspace(0.0, 0.02, W))
+        h = (rng.random((k, n, n)) * 1.1e-6).astype(np.float32)
+        u = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
+        tau = rng.random((W, f // b, f // b)).astype(np.float32)
+        a = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u], small_path=1)
+        r = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u])
+        assert r["plan"].uses_lds_path(), (n, pad)
+        for key in ("I", "L", "dh"):
+            assert torch_dev.equal(r[key], a[key]), (n, pad, key)
+        I_ref = o.forward(d, h, u, "fft")
+        assert per_wl_rel(r["I"].cpu().numpy().reshape(I_ref.shape), I_ref).max() <= INT_TOL
+
+
 def test_grouped_schedule_splits_large_groups(torch_dev):
     say("grouped schedule: 70 designs of one transform length (two launches per pass)")
     rng = np.random.default_rng(70)
