@@ -590,7 +590,8 @@ struct LdsGeo {
   static constexpr long long LDS_BYTES = 8LL * (static_cast<long long>(N) * RS + CB * CS + twiddle_count<M>());
   static constexpr bool FITS = LDS_BYTES <= 160 * 1024;
   // the forward's window field (F <= N) is staged in the column regions for the binning
-  static_assert(static_cast<long long>(CB) * CS >= static_cast<long long>(N) * N, "window staging");
+  static_assert(M > 128 || !FITS || static_cast<long long>(CB) * CS >= static_cast<long long>(N) * N,
+                "window staging");
 };
 
 // forward rows of one layer: FIRST = input field times t_0, else inverse row transform of the
