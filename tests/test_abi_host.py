@@ -89,6 +89,7 @@ def test_query_counts_transfer_tables(lib):
     ("dx", -1.0, dpx.DPX_E_ARG),
     ("dx", float("nan"), dpx.DPX_E_ARG),
     ("n", 80, dpx.DPX_E_UNSUPPORTED),
+    ("n_wl", 0, dpx.DPX_E_ARG),
 ])
 def test_query_rejects_bad_designs(lib, field, value, status):
     d = dict(wk.make_workload(1)["designs"][0])

@@ -131,7 +131,7 @@ def test_input_field_absorption_and_binning(torch_dev):
     assert err <= 1e-4
 
 
-@pytest.mark.parametrize("n", [64, 96, 128, 192, 256, 512])
+@pytest.mark.parametrize("n", [64, 96, 128, 192, 256, 512, 1024])
 def test_periodic_window_every_transform_length(torch_dev, n):
     say(f"pad 1 (periodic), N = M = {n}")
     g = np.random.default_rng(n)
@@ -166,6 +166,32 @@ def test_zero_padded_every_transform_length(torch_dev, n):
     _, g_ref, _ = o.loss(I_ref, tau)
     dh_ref = o.grad(d, h, None, g_ref, "fft")
     assert rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref) <= 1e-4
+
+
+def test_degenerate_zero_field_and_zero_target(torch_dev):
+    say("zero input field (zero intensity) and an all-zero target: finite loss, zero gradient")
+    g = np.random.default_rng(12)
+    wl = np.array([520e-9, 610e-9, 700e-9])
+    for small in (0, 1):
+        d = wk.make_design(n=64, layers=2, wl=wl, n_mat=1.5, dx=300e-9, z=[9e-6, 9e-6], fov=32, pad=2)
+        h = (g.random((2, 64, 64)) * 1e-6).astype(np.float32)
+        tau = g.random((3, 32, 32)).astype(np.float32)
+        tau[1] = 0.0
+        u0 = np.zeros((64, 64), np.complex64)
+        r = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u0], small_path=small)
+        I = r["I"].cpu().numpy()
+        assert not I.any()
+        L_ref, g_ref, _ = o.loss(np.zeros((3, 32, 32)), tau)
+        assert np.isfinite(r["L"].cpu().numpy()).all()
+        assert abs(float(r["L"].cpu()[0]) - L_ref) <= 1e-6 * max(L_ref, 1e-30)
+        assert not r["g"].cpu().numpy().any() and not g_ref.any()
+        assert not r["dh"].cpu().numpy().any()
+        # all-zero target with a live field: the target term drops out (sum rule)
+        r2 = run_gpu(torch_dev, [d], [h], [tau])
+        I2 = r2["I"].cpu().numpy().reshape(3, 32, 32)
+        L2_ref, g2_ref, _ = o.loss(I2.astype(np.float64), tau)
+        assert abs(float(r2["L"].cpu()[0]) - L2_ref) <= 1e-5 * L2_ref
+        assert rel_l2(r2["g"].cpu().numpy().reshape(3, 32, 32), g2_ref) <= 1e-5
 
 
 def test_single_layer_single_wavelength_edge(torch_dev):
