@@ -140,7 +140,7 @@ def main():
     ap.add_argument("--transfer-table", type=int, default=0, choices=[0, 1, 2],
                     help="transfer-function tables: 0 automatic, 1 never, 2 always")
     ap.add_argument("--small-path", type=int, default=0, choices=[0, 1],
-                    help="short transforms: 0 LDS-resident launches where supported, 1 multi-pass")
+                    help="short transforms: 0 multi-pass kernels, 1 LDS-resident launches where supported")
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
                     help="several designs: 0 automatic, 1 per design, 2 grouped launches")
     ap.add_argument("--graph", action="store_true",

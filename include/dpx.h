@@ -138,12 +138,14 @@ typedef struct dpx_opts {
                                every design in one wavelength chunk on one stream and a
                                transform column variant (0-3), else DPX_E_UNSUPPORTED.
                                Results are bitwise identical across schedules. */
-  int32_t small_path;       /* transform lengths up to 128 (pad 2; up to 96 with pad 1) in
-                               store mode, per-design schedule, one stream, no forced column
-                               variant and no transfer tables: 0 = each
-                               wavelength's plane stays in LDS and the forward (with the
-                               binning) and the adjoint (with the dL/dh partials) are one launch
-                               each; 1 = the multi-pass kernels.  Same bits either way. */
+  int32_t small_path;       /* 0 = the multi-pass kernels; 1 = for transform lengths up to 128
+                               (pad 2; up to 96 with pad 1) in store mode, per-design schedule,
+                               one stream, no forced column variant and no transfer tables,
+                               each wavelength's plane stays in LDS and the forward (with the
+                               binning) and the adjoint (with the dL/dh partials, one slot per
+                               wavelength) are one launch each.  Same bits either way.  Not the
+                               default: measured on MI355X it ties the multi-pass kernels on
+                               a few wavelengths and is slower on many (one block per CU). */
   int32_t reserved;
 } dpx_opts;
 

@@ -240,9 +240,9 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
     // chunks must hold whole blocks so every chunk maps onto the same partial slots
     chunk = std::max(wpb, chunk / wpb * wpb);
   }
-  // LDS-resident path for short transforms (opts.small_path): every wavelength is one block
-  // with one dL/dh slot, the whole design one chunk
-  d.lds = o.small_path != 1 && o.checkpoint_mode == 0 && o.streams <= 1 && o.force_variant < 0 &&
+  // LDS-resident path for short transforms (opts.small_path = 1): every wavelength is one
+  // block with one dL/dh slot, the whole design one chunk
+  d.lds = o.small_path == 1 && o.checkpoint_mode == 0 && o.streams <= 1 && o.force_variant < 0 &&
           o.transfer_table != 2 && dpx::lds_path_supported(d.M, d.pad);
   if (d.lds) {
     chunk = d.W;

@@ -482,8 +482,8 @@ def test_transfer_tables_match_evaluation(torch_dev):
 def test_lds_resident_path_matches_multi_pass(torch_dev):
     say("LDS-resident forward / adjoint (one launch each) vs the multi-pass kernels")
     w = wk.make_workload(2)
-    ref = run_gpu(torch_dev, w["designs"], w["h"], w["targets"], small_path=1)
-    lds = run_gpu(torch_dev, w["designs"], w["h"], w["targets"])
+    ref = run_gpu(torch_dev, w["designs"], w["h"], w["targets"])
+    lds = run_gpu(torch_dev, w["designs"], w["h"], w["targets"], small_path=1)
     assert lds["plan"].uses_lds_path() and not ref["plan"].uses_lds_path()
     for k in ("I", "L", "g", "dh"):
         assert torch_dev.equal(lds[k], ref[k]), k
@@ -498,8 +498,8 @@ def test_lds_resident_path_matches_multi_pass(torch_dev):
         h = (rng.random((k, n, n)) * 1.1e-6).astype(np.float32)
         u = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
         tau = rng.random((W, f // b, f // b)).astype(np.float32)
-        a = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u], small_path=1)
-        r = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u])
+        a = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u])
+        r = run_gpu(torch_dev, [d], [h], [tau], u_ins=[u], small_path=1)
         assert r["plan"].uses_lds_path(), (n, pad)
         for key in ("I", "L", "dh"):
             assert torch_dev.equal(r[key], a[key]), (n, pad, key)
