@@ -104,6 +104,7 @@ struct GroupLaunch {
   int M = 0, pad = 0, mode = 0, variant = 0;
   bool conj = false;
   bool table = false;      // column launches: the tasks read transfer tables
+  bool full = false;       // column launches: every task reads and keeps all aperture rows
   dpx::GroupArgs g{};
   int pass = -1;           // DPX_PASS_* of row / column launches (timers)
   int64_t bytes = 0;       // algorithmic bytes (without the input field)
@@ -649,10 +650,11 @@ struct ColItem {
 
 void add_col_position(dpx_plan* p, const std::vector<ColItem>& items, bool conj,
                       std::vector<GroupLaunch>& out, TaskBlob& blob) {
-  std::map<std::array<int, 4>, std::vector<ColItem>> by_key;
+  std::map<std::array<int, 5>, std::vector<ColItem>> by_key;
   for (const auto& it : items) {
     const Design& d = p->designs[it.design];
-    by_key[{d.M, d.pad, d.col_variant, d.htab ? 1 : 0}].push_back(it);
+    const bool full = it.in_lo == 0 && it.in_hi == d.N && it.out_lo == 0 && it.out_hi == d.N;
+    by_key[{d.M, d.pad, d.col_variant, d.htab ? 1 : 0, full ? 1 : 0}].push_back(it);
   }
   for (const auto& kv : by_key) {
     std::vector<dpx::ColTask> tasks;
@@ -679,6 +681,7 @@ void add_col_position(dpx_plan* p, const std::vector<ColItem>& items, bool conj,
     proto.pad = kv.first[1];
     proto.variant = kv.first[2];
     proto.table = kv.first[3] != 0;
+    proto.full = kv.first[4] != 0;
     proto.conj = conj;
     proto.pass = conj ? DPX_PASS_COL_ADJ : DPX_PASS_COL_FWD;
     add_group(out, proto, tasks, nb, al, by, ub, fl, blob);
@@ -832,7 +835,7 @@ dpx_status run_groups(dpx_plan* p, const std::vector<GroupLaunch>& launches, con
     hipError_t e = hipErrorInvalidValue;
     switch (L.kind) {
       case GK_ROW: e = dpx::launch_row_group(L.M, L.pad, L.mode, g, s); break;
-      case GK_COL: e = dpx::launch_col_group(L.M, L.pad, L.conj, L.variant, L.table, g, s); break;
+      case GK_COL: e = dpx::launch_col_group(L.M, L.pad, L.conj, L.variant, L.table, L.full, g, s); break;
       case GK_BIN: e = dpx::launch_bin_group(g, out_f, s); break;
       case GK_DH: e = dpx::launch_dh_group(g, out_f, s); break;
       case GK_LOSS: break;

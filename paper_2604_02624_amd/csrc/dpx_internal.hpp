@@ -188,8 +188,8 @@ __device__ __forceinline__ int group_task(const GroupArgs& g, int b) {
                             hipStream_t s);                                                             \
   hipError_t launch_row_group_##m(int pad, int mode, const GroupArgs& g, hipStream_t s);                \
   hipError_t launch_col_##m(int pad, bool conj, int variant, const ColArgs& a, int w_count, hipStream_t s); \
-  hipError_t launch_col_group_##m(int pad, bool conj, int variant, bool table, const GroupArgs& g,       \
-                                  hipStream_t s);                                                       \
+  hipError_t launch_col_group_##m(int pad, bool conj, int variant, bool table, bool full,               \
+                                  const GroupArgs& g, hipStream_t s);                                   \
   hipError_t launch_transfer_table_##m(const WlConst* wl, int W, double zrev, float2* out, hipStream_t s); \
   hipError_t launch_lds_##m(int pad, bool adjoint, const LdsArgs& a, hipStream_t s);                     \
   bool lds_supported_##m(int pad);
@@ -197,8 +197,9 @@ DPX_FOR_EACH_M(DPX_DECLARE_PASS_LAUNCHERS)
 #undef DPX_DECLARE_PASS_LAUNCHERS
 
 hipError_t launch_row_group(int M, int pad, int mode, const GroupArgs& g, hipStream_t s);
-// table: every task's arguments carry a transfer table (else none does)
-hipError_t launch_col_group(int M, int pad, bool conj, int variant, bool table, const GroupArgs& g,
+// table: every task's arguments carry a transfer table (else none does); full: every task reads
+// and keeps all its aperture rows
+hipError_t launch_col_group(int M, int pad, bool conj, int variant, bool table, bool full, const GroupArgs& g,
                             hipStream_t s);
 hipError_t launch_bin_group(const GroupArgs& g, float* out, hipStream_t s);
 hipError_t launch_loss_group(const GroupArgs& g, const float* I, const float* tau, float* dl_di,

@@ -279,11 +279,11 @@ hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, 
   }
 }
 
-hipError_t launch_col_group(int M, int pad, bool conj, int variant, bool table, const GroupArgs& g,
+hipError_t launch_col_group(int M, int pad, bool conj, int variant, bool table, bool full, const GroupArgs& g,
                             hipStream_t s) {
   if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks || variant < 0 || variant > 3) return hipErrorInvalidValue;
   switch (M) {
-#define DPX_CASE(m) case m: return launch_col_group_##m(pad, conj, variant, table, g, s);
+#define DPX_CASE(m) case m: return launch_col_group_##m(pad, conj, variant, table, full, g, s);
     DPX_FOR_EACH_M(DPX_CASE)
 #undef DPX_CASE
     default:

@@ -57,13 +57,20 @@ hipError_t row_group_mode(int mode, const GroupArgs& g, hipStream_t s) {
 // H source of a launch: the table when the arguments carry one, else the variant's evaluation
 int h_mode(int variant, bool table) { return table ? kHTable : (variant >= 2 ? kHMirror : kHEval); }
 
+// every aperture row in and out (the row-range tests compile away)
+bool full_rows(const ColArgs& a) { return a.in_lo == 0 && a.out_lo == 0 && a.in_hi == a.n && a.out_hi == a.n; }
+
 template <int PAD, int TX, int HM>
 hipError_t col_launch(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
   dim3 grid(M / TX, (w_count + a.col_wpb - 1) / a.col_wpb);
-  if (conj)
-    col_kernel<M, PAD, true, TX, HM><<<grid, TX * Geo<M>::P, 0, s>>>(a);
-  else
-    col_kernel<M, PAD, false, TX, HM><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+  const bool full = full_rows(a);
+  if (conj) {
+    if (full) col_kernel<M, PAD, true, TX, HM, true><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+    else col_kernel<M, PAD, true, TX, HM, false><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+  } else {
+    if (full) col_kernel<M, PAD, false, TX, HM, true><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+    else col_kernel<M, PAD, false, TX, HM, false><<<grid, TX * Geo<M>::P, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -98,26 +105,29 @@ hipError_t colgemm_launch(bool conj, const ColArgs& a, int w_count, hipStream_t 
 }
 
 template <int PAD, int TX, int HM>
-hipError_t col_group_tx(bool conj, const GroupArgs& g, hipStream_t s) {
-  if (conj)
-    col_group_kernel<M, PAD, true, TX, HM><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
-  else
-    col_group_kernel<M, PAD, false, TX, HM><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+hipError_t col_group_tx(bool conj, bool full, const GroupArgs& g, hipStream_t s) {
+  if (conj) {
+    if (full) col_group_kernel<M, PAD, true, TX, HM, true><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+    else col_group_kernel<M, PAD, true, TX, HM, false><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+  } else {
+    if (full) col_group_kernel<M, PAD, false, TX, HM, true><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+    else col_group_kernel<M, PAD, false, TX, HM, false><<<group_grid(g), TX * Geo<M>::P, 0, s>>>(g);
+  }
   return hipGetLastError();
 }
 
 template <int PAD, int TX>
-hipError_t col_group_h(int hm, bool conj, const GroupArgs& g, hipStream_t s) {
-  if (hm == kHTable) return col_group_tx<PAD, TX, kHTable>(conj, g, s);
-  if (hm == kHMirror) return col_group_tx<PAD, TX, kHMirror>(conj, g, s);
-  return col_group_tx<PAD, TX, kHEval>(conj, g, s);
+hipError_t col_group_h(int hm, bool conj, bool full, const GroupArgs& g, hipStream_t s) {
+  if (hm == kHTable) return col_group_tx<PAD, TX, kHTable>(conj, full, g, s);
+  if (hm == kHMirror) return col_group_tx<PAD, TX, kHMirror>(conj, full, g, s);
+  return col_group_tx<PAD, TX, kHEval>(conj, full, g, s);
 }
 
 template <int PAD>
-hipError_t col_group_variant(int variant, bool table, bool conj, const GroupArgs& g, hipStream_t s) {
+hipError_t col_group_variant(int variant, bool table, bool conj, bool full, const GroupArgs& g, hipStream_t s) {
   const int hm = h_mode(variant, table);
-  if (col_tile_width(M, variant) == 8) return col_group_h<PAD, 8>(hm, conj, g, s);
-  return col_group_h<PAD, 16>(hm, conj, g, s);
+  if (col_tile_width(M, variant) == 8) return col_group_h<PAD, 8>(hm, conj, full, g, s);
+  return col_group_h<PAD, 16>(hm, conj, full, g, s);
 }
 
 }  // namespace
@@ -147,10 +157,10 @@ hipError_t DPX_NAME(launch_col_)(int pad, bool conj, int variant, const ColArgs&
   return hipErrorInvalidValue;
 }
 
-hipError_t DPX_NAME(launch_col_group_)(int pad, bool conj, int variant, bool table, const GroupArgs& g,
+hipError_t DPX_NAME(launch_col_group_)(int pad, bool conj, int variant, bool table, bool full, const GroupArgs& g,
                                        hipStream_t s) {
-  if (pad == 2) return col_group_variant<2>(variant, table, conj, g, s);
-  if (pad == 1) return col_group_variant<1>(variant, table, conj, g, s);
+  if (pad == 2) return col_group_variant<2>(variant, table, conj, full, g, s);
+  if (pad == 1) return col_group_variant<1>(variant, table, conj, full, g, s);
   return hipErrorInvalidValue;
 }
 

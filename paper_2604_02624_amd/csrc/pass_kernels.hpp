@@ -269,7 +269,7 @@ constexpr int kHEval = 0, kHMirror = 1, kHTable = 2;
 
 // Block (bx, by) of a column pass: column tile bx of gx, wavelength block by.  The blocks of
 // one pass are numbered bx + gx by from a multiple of 16 in launch order.
-template <int M, int PAD, bool CONJ, int TX, int HM>
+template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL>
 __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int gx, float2* tile, float2* tw) {
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
@@ -305,20 +305,24 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
   constexpr bool PREFETCH = HALF;
   const int wb = by * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
-  const unsigned voff = static_cast<unsigned>(((a.in_lo + yy) * M + kx0 + cc) * 8);
+  const unsigned voff = static_cast<unsigned>((((FULL ? 0 : a.in_lo) + yy) * M + kx0 + cc) * 8);
   auto plane = [&](int w) {
     return __builtin_amdgcn_make_buffer_rsrc(a.spec + static_cast<size_t>(w) * N * M, 0,
                                              N * M * 8, kBufferRsrcWord3);
   };
+  // FULL: the pass reads and keeps every aperture row (all passes but the first adjoint and
+  // the last forward one), so the row-range tests drop out.
+  const int in_lo = FULL ? 0 : a.in_lo, in_hi = FULL ? N : a.in_hi;
+  const int out_lo = FULL ? 0 : a.out_lo, out_hi = FULL ? N : a.out_hi;
   float2 pre[PREFETCH ? EN : 1];
   auto fetch = [&](int w) {
     const auto rs = plane(w);
 #pragma unroll
     for (int k = 0; k < EN; ++k) {
-      const int y = a.in_lo + yy + k * P;
-      pre[PREFETCH ? k : 0] = (y < a.in_hi) ? buffer_load_c64(rs, voff, k * P * M * 8) : make_float2(0.f, 0.f);
+      const int y = in_lo + yy + k * P;
+      pre[PREFETCH ? k : 0] = (y < in_hi) ? buffer_load_c64(rs, voff, k * P * M * 8) : make_float2(0.f, 0.f);
       if constexpr (!PREFETCH) {
-        if (y < a.in_hi) tile[cc * LD + y] = pre[0];
+        if (y < in_hi) tile[cc * LD + y] = pre[0];
       }
     }
   };
@@ -329,8 +333,8 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
     if constexpr (PREFETCH) {
 #pragma unroll
       for (int k = 0; k < EN; ++k) {
-        const int y = a.in_lo + yy + k * P;
-        if (y < a.in_hi) tile[cc * LD + y] = pre[k];
+        const int y = in_lo + yy + k * P;
+        if (y < in_hi) tile[cc * LD + y] = pre[k];
       }
     } else {
       fetch(w);
@@ -345,7 +349,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
       const int y = j0 + P * t;
-      reg[t] = (y >= a.in_lo && y < a.in_hi) ? lds[y] : make_float2(0.f, 0.f);
+      reg[t] = (y >= in_lo && y < in_hi) ? lds[y] : make_float2(0.f, 0.f);
     }
     wave_sync();
     fft<M, false, HALF>(reg, lds, j0, tw);
@@ -396,26 +400,31 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
       const int y = j0 + P * t;
-      if (y >= a.out_lo && y < a.out_hi) lds[y] = reg[t];
+      if (y >= out_lo && y < out_hi) lds[y] = reg[t];
     }
     __syncthreads();
     float2* sp = a.spec + static_cast<size_t>(w) * N * M + kx0 + cc;
-    for (int y = a.out_lo + yy; y < a.out_hi; y += P) sp[static_cast<size_t>(y) * M] = tile[cc * LD + y];
+    if constexpr (FULL) {
+#pragma unroll
+      for (int k = 0; k < EN; ++k) sp[static_cast<size_t>(yy + k * P) * M] = tile[cc * LD + yy + k * P];
+    } else {
+      for (int y = out_lo + yy; y < out_hi; y += P) sp[static_cast<size_t>(y) * M] = tile[cc * LD + y];
+    }
     __syncthreads();  // the next wavelength's staging overwrites the tile
   }
 }
 
-template <int M, int PAD, bool CONJ, int TX, int HM>
+template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL>
 __global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_per_eu(4)))
 col_kernel(ColArgs a) {
   __shared__ float2 tile[TX * Geo<M>::COL_REGION];
   __shared__ float2 tw[twiddle_count<M>()];
-  col_body<M, PAD, CONJ, TX, HM>(a, blockIdx.x, blockIdx.y, gridDim.x, tile, tw);
+  col_body<M, PAD, CONJ, TX, HM, FULL>(a, blockIdx.x, blockIdx.y, gridDim.x, tile, tw);
 }
 
 // One launch of a column pass for several designs of the same transform length (see
 // row_group_kernel); every task starts at a multiple of 16 blocks.
-template <int M, int PAD, bool CONJ, int TX, int HM>
+template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL>
 __global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_per_eu(4)))
 col_group_kernel(GroupArgs g) {
   __shared__ float2 tile[TX * Geo<M>::COL_REGION];
@@ -425,7 +434,7 @@ col_group_kernel(GroupArgs g) {
   const int local = static_cast<int>(blockIdx.x) - g.block0[ti];
   if (local >= t.nblocks) return;
   const ColArgs a = t.a;
-  col_body<M, PAD, CONJ, TX, HM>(a, local % t.gx, local / t.gx, t.gx, tile, tw);
+  col_body<M, PAD, CONJ, TX, HM, FULL>(a, local % t.gx, local / t.gx, t.gx, tile, tw);
 }
 
 // H / M^2 of one gap for every wavelength on the quarter plane |kx|, |ky| <= M/2 (H depends on
