@@ -326,18 +326,25 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
       }
     }
   };
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < EN; ++k) {
+      const int y = in_lo + yy + k * P;
+      if (y < in_hi) tile[cc * LD + y] = pre[k];
+    }
+  };
+  // With every row in and out, the tile elements a thread stages for the next wavelength are
+  // exactly those it copies out for the current one, so the staging follows the copy-out
+  // without a barrier between them.
+  constexpr bool STAGE_AFTER_STORE = FULL && PREFETCH;
   if constexpr (PREFETCH) fetch(wb);
   stage_twiddles<M>(tw, a.tw, threadIdx.x, NT);
+  if constexpr (STAGE_AFTER_STORE) stage();
 
   for (int w = wb; w < we; ++w) {
-    if constexpr (PREFETCH) {
-#pragma unroll
-      for (int k = 0; k < EN; ++k) {
-        const int y = in_lo + yy + k * P;
-        if (y < in_hi) tile[cc * LD + y] = pre[k];
-      }
-    } else {
-      fetch(w);
+    if constexpr (!STAGE_AFTER_STORE) {
+      if constexpr (PREFETCH) stage();
+      else fetch(w);
     }
     __syncthreads();
     if constexpr (PREFETCH) {
@@ -410,7 +417,11 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
     } else {
       for (int y = out_lo + yy; y < out_hi; y += P) sp[static_cast<size_t>(y) * M] = tile[cc * LD + y];
     }
-    __syncthreads();  // the next wavelength's staging overwrites the tile
+    if constexpr (STAGE_AFTER_STORE) {
+      if (w + 1 < we) stage();
+    } else {
+      __syncthreads();  // the next wavelength's staging overwrites the tile
+    }
   }
 }
 
