@@ -109,7 +109,14 @@ def cpu_baseline(d, h, tau, budget_s):
         o.grad(d, h, None, g, "fft", wavelengths=[w])
         done += 1
     dt = time.perf_counter() - t0
-    return dict(value=done * K / dt, unit=UNIT, cores=1, kind="oracle",
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=done * K / dt, unit=UNIT, cores=1, kind="oracle", host_cpus=os.cpu_count(),
+                cpu_model=model,
                 sample=f"{done} wavelengths x {K} layers of the same workload, forward + loss + "
                        f"adjoint, numpy.fft (pocketfft, single thread) FP64, {dt:.1f} s")
 
