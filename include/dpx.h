@@ -47,7 +47,9 @@
  *   - Every call returns a dpx_status; no exception crosses this interface.  On failure
  *     dpx_last_error() gives a message for the calling thread.
  *   - The plan owns all scratch memory (allocated in dpx_plan_create, released in
- *     dpx_plan_destroy).  dpx_forward, dpx_loss and dpx_backward allocate nothing.
+ *     dpx_plan_destroy).  dpx_forward, dpx_loss and dpx_backward allocate no device memory
+ *     (with opts.use_graph the first call per pointer set instantiates a HIP graph, and the
+ *     per-pass timers create HIP events: runtime objects, not workspace).
  *   - A plan is not thread-safe; distinct plans are independent.
  */
 #ifndef DPX_H
@@ -62,7 +64,9 @@ extern "C" {
 typedef enum dpx_status {
   DPX_OK = 0,
   DPX_E_ARG = 1,          /* invalid argument: null pointer, bad shape, misaligned buffer */
-  DPX_E_UNSUPPORTED = 2,  /* valid but not built: transform length pad*N not in the table */
+  DPX_E_UNSUPPORTED = 2,  /* valid but not built or not applicable: transform length pad*N
+                             not in the table, a forced column variant not built for it, the
+                             grouped schedule asked for where it cannot run */
   DPX_E_NOMEM = 3,        /* device allocation failed or exceeds opts.max_workspace_bytes */
   DPX_E_DEVICE = 4,       /* a HIP runtime error (launch failure, earlier async fault) */
   DPX_E_STATE = 5         /* call order: store-mode backward without a matching forward */
@@ -170,8 +174,10 @@ void dpx_opts_default(dpx_opts* opts);
 /* Validates the designs, copies their host arrays, builds the per-wavelength constant
  * tables and twiddle tables, and allocates every device buffer the calls need on the
  * current HIP device.  designs: [n_designs] host array; opts may be NULL (defaults).
- * On success *out owns the plan.  Errors: DPX_E_ARG (shape rules above), DPX_E_UNSUPPORTED
- * (pad*N not one of 64, 96, 128, 192, 256, 384, 512, 1024), DPX_E_NOMEM, DPX_E_DEVICE. */
+ * On success *out owns the plan.  Errors: DPX_E_ARG (shape rules above, option ranges),
+ * DPX_E_UNSUPPORTED (pad*N not one of 64, 96, 128, 192, 256, 384, 512, 1024; a forced column
+ * variant not built for a design; schedule 2 where it cannot run), DPX_E_NOMEM,
+ * DPX_E_DEVICE. */
 dpx_status dpx_plan_create(const dpx_design* designs, int32_t n_designs, const dpx_opts* opts,
                            dpx_plan** out);
 

@@ -1086,12 +1086,18 @@ dpx_status dpx_plan_query(const dpx_design* ds, int32_t nd, const dpx_opts* opts
   if (!bytes) return fail(DPX_E_ARG, "workspace_bytes is NULL");
   int64_t tot = 0;
   std::map<int, int> ms;
+  bool groupable_all = o.checkpoint_mode == 0;
   for (int i = 0; i < nd; ++i) {
     Design d;
     layout_design(ds[i], o, d);
     tot += d.bytes;
     ms[d.M] = 1;
+    groupable_all = groupable_all && d.nchunks == 1 && d.lanes == 1 && d.col_variant <= 3;
   }
+  if (o.schedule == 2 && !groupable_all)
+    return fail(DPX_E_UNSUPPORTED,
+                "the grouped schedule needs checkpoint_mode 0, every design in one wavelength chunk "
+                "on one stream, and a transform column variant (0-3)");
   for (auto& kv : ms) tot += static_cast<int64_t>(kv.first) * 8;
   *bytes = tot;
   return ok();

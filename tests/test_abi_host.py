@@ -128,6 +128,9 @@ def test_query_rejects_bad_options(lib):
     with pytest.raises(dpx.DpxError):
         _query([d], small_path=2)
     assert _query([d], schedule=2) > 0
+    with pytest.raises(dpx.DpxError) as e:
+        _query([d], schedule=2, checkpoint_mode=1)
+    assert e.value.status == dpx.DPX_E_UNSUPPORTED
 
 
 def test_null_plan_and_pointers_are_errors(lib):
