@@ -324,3 +324,65 @@ def rs_direct(u: np.ndarray, dx: float, wl: float, n_medium: float, z: float) ->
         blocks = T[py - sy + N - 1]                                      # [N(sy), N(px), N(sx)]
         out[py] = np.einsum("spk,sk->p", blocks, u)
     return out
+
+
+# ------------------------------------------------------------------------------------------
+# Training support (Section 4, "Data preparation and other implementation details": Adam with
+# the optimizer library's default parameters, learning rate 0.001; Section 2: output PSNR per
+# image-wavelength pair).  Readings: the heights are kept in [0, h_max] through an
+# unconstrained variable, h = h_max * sigmoid(theta) (the paper does not say how its bound is
+# enforced), and PSNR is the textbook one on the unit-sum normalised images with the target's
+# peak (the paper's convention is in its missing supplement).
+# ------------------------------------------------------------------------------------------
+ADAM_DEFAULTS = dict(lr=1e-3, b1=0.9, b2=0.999, eps=1e-8)
+
+
+def sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def adam_update(g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """Adam (Kingma and Ba): moment estimates, bias correction by 1 - b^step, and the step
+    -lr * m_hat / (sqrt(v_hat) + eps).  Returns (delta, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** step)
+    v_hat = v / (1.0 - b2 ** step)
+    return -lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def adam_sigmoid_step(theta, dl_dh, m, v, step, h_max, **adam):
+    """One step on theta given dL/dh for h = h_max sigmoid(theta): chain rule
+    dL/dtheta = dL/dh * h_max s (1 - s), Adam on theta.  Returns (theta, h, m, v)."""
+    s = sigmoid(theta)
+    g = dl_dh * h_max * s * (1.0 - s)
+    delta, m, v = adam_update(g, m, v, step, **{**ADAM_DEFAULTS, **adam})
+    theta = theta + delta
+    return theta, h_max * sigmoid(theta), m, v
+
+
+def psnr(I: np.ndarray, tau: np.ndarray) -> np.ndarray:
+    """Per wavelength: 10 log10(max tau_hat^2 / mean (I_hat - tau_hat)^2), both images
+    normalised to unit sum (a zero sum normalises to zero, as in the loss)."""
+    I = np.asarray(I, np.float64)
+    tau = np.asarray(tau, np.float64)
+    W = I.shape[0]
+    out = np.empty(W)
+    for w in range(W):
+        S, St = I[w].sum(), tau[w].sum()
+        a = I[w] / S if S > 0 else np.zeros_like(I[w])
+        b = tau[w] / St if St > 0 else np.zeros_like(tau[w])
+        mse = np.mean((a - b) ** 2)
+        out[w] = np.inf if mse == 0 else 10.0 * np.log10(b.max() ** 2 / mse)
+    return out
+
+
+def channel_swap(psnr_per_wl: np.ndarray, wl: np.ndarray) -> np.ndarray:
+    """Dynamic channel swapping (Section 2): images sorted by PSNR, highest first, are
+    reassigned to the wavelengths taken from the longest down.  Returns src such that the new
+    target of wavelength w is the old target of wavelength src[w]."""
+    by_psnr = np.argsort(-np.asarray(psnr_per_wl), kind="stable")
+    by_length = np.argsort(-np.asarray(wl), kind="stable")
+    src = np.empty(len(wl), dtype=np.int64)
+    src[by_length] = by_psnr
+    return src

@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import tests.test_oracle_pins as pins
+import tests.test_oracle_training as tpins
 from oracle import dpx_oracle as o
 
 TWO_PI = 2 * np.pi
@@ -55,6 +56,42 @@ def _loss_missing_inner(I, tau):
 
 
 _orig_loss = o.loss
+_orig_adam = o.adam_update
+
+
+def _adam_no_bias_correction(g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    return -lr * m / (np.sqrt(v) + eps), m, v
+
+
+def _adam_eps_inside(g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    return -lr * (m / (1 - b1 ** step)) / np.sqrt(v / (1 - b2 ** step) + eps), m, v
+
+
+def _sigmoid_wrong_slope(x):
+    return 1.0 / (1.0 + np.exp(-2.0 * x))
+
+
+def _psnr_image_peak(I, tau):
+    I = np.asarray(I, float)
+    tau = np.asarray(tau, float)
+    out = []
+    for w in range(I.shape[0]):
+        a, b = I[w] / I[w].sum(), tau[w] / tau[w].sum()
+        mse = np.mean((a - b) ** 2)
+        out.append(np.inf if mse == 0 else 10 * np.log10(a.max() ** 2 / mse))
+    return np.array(out)
+
+
+def _swap_shortest_first(ps, wl):
+    by_psnr = np.argsort(-np.asarray(ps), kind="stable")
+    by_length = np.argsort(np.asarray(wl), kind="stable")
+    src = np.empty(len(wl), dtype=np.int64)
+    src[by_length] = by_psnr
+    return src
 
 CASES = [
     ("transfer_function", _h_sign_flipped, [pins.test_tilted_plane_wave, (3, 0)]),
@@ -65,6 +102,11 @@ CASES = [
     ("transmission", _t_sign_flipped, [pins.test_prism_deflects_toward_thicker_side]),
     ("transmission", _t_index_not_relative, [pins.test_prism_deflects_toward_thicker_side]),
     ("loss", _loss_missing_inner, [pins.test_loss_gradient_finite_difference_and_euler]),
+    ("adam_update", _adam_no_bias_correction, [tpins.test_adam_constant_gradient_closed_form]),
+    ("adam_update", _adam_eps_inside, [tpins.test_adam_constant_gradient_closed_form]),
+    ("sigmoid", _sigmoid_wrong_slope, [tpins.test_sigmoid_step_follows_the_chain_rule]),
+    ("psnr", _psnr_image_peak, [tpins.test_psnr_of_a_known_perturbation]),
+    ("channel_swap", _swap_shortest_first, [tpins.test_channel_swap_assigns_best_images_to_longest_wavelengths]),
 ]
 
 
