@@ -219,6 +219,29 @@ dpx_status dpx_loss(dpx_plan* plan, const float* intensity, const float* target,
 dpx_status dpx_backward(dpx_plan* plan, const float* h, const float* u_in, const float* dl_di,
                         float* dl_dh, void* stream);
 
+/* Per-wavelength PSNR of the intensity images against the targets (evaluation, Section 2:
+ * output PSNR per image-wavelength pair), both normalised to unit sum as in the loss:
+ *   psnr_w = 10 log10( max_p tau_w,p^2 / mean_p (I_w,p - tau_w,p)^2 )   (normalised images)
+ * The paper's peak convention is in its missing supplement; this is the textbook PSNR with the
+ * target's peak.  intensity, target [sum W T T] (device, read); psnr [sum W] doubles, designs
+ * in order (device, written; +inf where the images agree exactly). */
+dpx_status dpx_psnr(dpx_plan* plan, const float* intensity, const float* target, double* psnr,
+                    void* stream);
+
+/* One optimizer step for training the heights (Section 4: Adam with the optimizer library's
+ * defaults b1 = 0.9, b2 = 0.999, eps = 1e-8 and learning rate 0.001).  The heights are bounded
+ * to [0, h_max] through an unconstrained variable, h = h_max sigmoid(theta); given
+ * dl_dh = dL/dh (dpx_backward) the step updates, for each of the n elements,
+ *   g = dl_dh h_max s (1 - s)   (s = sigmoid(theta)),
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   theta -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
+ *   h = h_max sigmoid(theta).
+ * theta, h, m, v [n] (device, read and written; m and v start at 0), dl_dh [n] (device, read);
+ * step counts from 1.  Single precision; the bias corrections are formed in double. */
+dpx_status dpx_adam_step(float* theta, float* h, const float* dl_dh, float* m, float* v, int64_t n,
+                         int32_t step, double lr, double b1, double b2, double eps, double h_max,
+                         void* stream);
+
 /* Pass kinds reported by the per-pass timers. */
 typedef enum dpx_pass {
   DPX_PASS_COL_FWD = 0,       /* column pass with H (forward) */

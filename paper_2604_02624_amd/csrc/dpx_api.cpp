@@ -1473,6 +1473,50 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
   return ok();
 }
 
+dpx_status dpx_psnr(dpx_plan* p, const float* intensity, const float* target, double* psnr, void* stream) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  DPX_TRY(check_ptr(intensity, 4, "intensity"));
+  DPX_TRY(check_ptr(target, 4, "target"));
+  DPX_TRY(check_ptr(psnr, 8, "psnr"));
+  DPX_TRY(sticky_check());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t w_off = 0;
+  for (const auto& d : p->designs) {
+    hipError_t e = dpx::launch_psnr(intensity + d.img_off, target + d.img_off, psnr + w_off, d.W, d.T, s);
+    if (e != hipSuccess) return fail(DPX_E_DEVICE, "PSNR launch failed: %s", hipGetErrorString(e));
+    w_off += d.W;
+  }
+  return ok();
+}
+
+dpx_status dpx_adam_step(float* theta, float* h, const float* dl_dh, float* m, float* v, int64_t n, int32_t step,
+                         double lr, double b1, double b2, double eps, double h_max, void* stream) {
+  if (n < 0) return fail(DPX_E_ARG, "n must be >= 0");
+  if (n == 0) return ok();
+  DPX_TRY(check_ptr(theta, 4, "theta"));
+  DPX_TRY(check_ptr(h, 4, "h"));
+  DPX_TRY(check_ptr(dl_dh, 4, "dl_dh"));
+  DPX_TRY(check_ptr(m, 4, "m"));
+  DPX_TRY(check_ptr(v, 4, "v"));
+  if (step < 1) return fail(DPX_E_ARG, "step counts from 1 (got %d)", step);
+  if (!(lr > 0.0) || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) || !(eps >= 0.0) || !(h_max > 0.0))
+    return fail(DPX_E_ARG, "need lr > 0, 0 <= b1, b2 < 1, eps >= 0, h_max > 0");
+  DPX_TRY(sticky_check());
+  dpx::AdamArgs a{};
+  a.lr = static_cast<float>(lr);
+  a.b1 = static_cast<float>(b1);
+  a.b2 = static_cast<float>(b2);
+  a.eps = static_cast<float>(eps);
+  a.h_max = static_cast<float>(h_max);
+  a.omb1 = static_cast<float>(1.0 - b1);
+  a.omb2 = static_cast<float>(1.0 - b2);
+  a.c1 = static_cast<float>(1.0 / (1.0 - std::pow(b1, step)));
+  a.c2 = static_cast<float>(1.0 / (1.0 - std::pow(b2, step)));
+  hipError_t e = dpx::launch_adam_sigmoid(theta, h, dl_dh, m, v, n, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "Adam step launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 dpx_status dpx_timing_enable(dpx_plan* p, int32_t enable) {
   if (!p) return fail(DPX_E_ARG, "plan is NULL");
   for (auto& t : p->pending) {

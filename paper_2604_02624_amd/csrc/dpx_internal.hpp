@@ -232,6 +232,17 @@ hipError_t launch_dh_reduce(const float* part, float* dh, int nchunk, int64_t pe
                             hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 
+// Adam on theta with h = h_max sigmoid(theta) (see adam_sigmoid_kernel)
+struct AdamArgs {
+  float lr, b1, b2, eps, h_max;
+  float omb1, omb2;  // 1 - b1, 1 - b2 (formed in double)
+  float c1, c2;      // 1 / (1 - b1^t), 1 / (1 - b2^t)
+};
+hipError_t launch_adam_sigmoid(float* theta, float* h, const float* dl_dh, float* m, float* v, int64_t n,
+                               const AdamArgs& a, hipStream_t s);
+// per-wavelength PSNR of one design's [W][T][T] images -> out [W]
+hipError_t launch_psnr(const float* I, const float* tau, double* out, int W, int T, hipStream_t s);
+
 bool fft_size_supported(int M);
 // host: per-stage twiddle table of the length-M transform (layout in fft.hpp)
 void build_twiddle_table(int M, std::vector<float2>& out);

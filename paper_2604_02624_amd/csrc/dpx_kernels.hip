@@ -140,6 +140,74 @@ __global__ void dh_group_kernel(GroupArgs g, float* __restrict__ dl_dh) {
                  static_cast<int64_t>(local) * blockDim.x + threadIdx.x);
 }
 
+// ------------------------------------------------------------------------------------------
+// Training support (Section 4: Adam with the optimizer library's defaults; heights bounded to
+// [0, h_max] through a sigmoid of an unconstrained variable)
+// ------------------------------------------------------------------------------------------
+// One Adam step on theta with h = h_max sigmoid(theta):
+//   g = dL/dh * h_max s (1 - s),  m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+//   theta -= lr (m c1) / (sqrt(v c2) + eps)  with c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t),
+// then h = h_max sigmoid(theta).  Arithmetic in single precision; 1 - b1, 1 - b2 and the bias
+// corrections come from the host, formed in double.
+__global__ void adam_sigmoid_kernel(float* __restrict__ theta, float* __restrict__ h, const float* __restrict__ dl_dh,
+                                    float* __restrict__ m, float* __restrict__ v, int64_t n, AdamArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float th = theta[i];
+  // s (1 - s) = e / (1 + e)^2 with e = exp(-|theta|): even in theta, no cancellation near
+  // s = 1 and no overflow for large |theta|.
+  const float e = expf(-fabsf(th));
+  const float ope = 1.0f + e;
+  const float g = dl_dh[i] * (a.h_max * (e / (ope * ope)));
+  const float mi = fmaf(a.b1, m[i], a.omb1 * g);
+  const float vi = fmaf(a.b2, v[i], a.omb2 * (g * g));
+  m[i] = mi;
+  v[i] = vi;
+  const float t2 = th - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+  theta[i] = t2;
+  h[i] = a.h_max / (1.0f + expf(-t2));
+}
+
+// Per-wavelength PSNR of the intensity image against its target, both normalised to unit sum
+// (as in the loss): 10 log10(max_p tau^2 / mean_p (I - tau)^2), in double; one block per
+// wavelength of one design ([W][T][T] images, out [W]).
+__global__ void __launch_bounds__(kLossThreads)
+psnr_kernel(const float* __restrict__ I, const float* __restrict__ tau, double* __restrict__ out, int T) {
+  __shared__ double sh[kLossThreads];
+  const int w = blockIdx.x;
+  const int P = T * T;
+  const float* Iw = I + static_cast<size_t>(w) * P;
+  const float* tw = tau + static_cast<size_t>(w) * P;
+  double si = 0.0, st = 0.0, mx = 0.0;
+  for (int p = threadIdx.x; p < P; p += kLossThreads) {
+    si += Iw[p];
+    st += tw[p];
+    mx = fmax(mx, static_cast<double>(tw[p]));
+  }
+  const double S = block_sum(si, sh);
+  const double St = block_sum(st, sh);
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kLossThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double tmax = sh[0];
+  __syncthreads();
+  const double rS = S > 0.0 ? 1.0 / S : 0.0;
+  const double rSt = St > 0.0 ? 1.0 / St : 0.0;
+  double sd2 = 0.0;
+  for (int p = threadIdx.x; p < P; p += kLossThreads) {
+    const double d = Iw[p] * rS - tw[p] * rSt;
+    sd2 += d * d;
+  }
+  const double mse = block_sum(sd2, sh) / P;
+  if (threadIdx.x == 0) {
+    const double peak = tmax * rSt;
+    out[w] = (mse > 0.0) ? 10.0 * log10(peak * peak / mse) : INFINITY;
+  }
+}
+
 __global__ void fill_zero_kernel(float* p, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
@@ -377,6 +445,20 @@ hipError_t launch_loss_sum_group(const LossTask* tasks, int ntasks, double* loss
 hipError_t launch_dh_group(const GroupArgs& g, float* dl_dh, hipStream_t s) {
   if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks) return hipErrorInvalidValue;
   dh_group_kernel<<<group_grid(g), kGroupThreads, 0, s>>>(g, dl_dh);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_sigmoid(float* theta, float* h, const float* dl_dh, float* m, float* v, int64_t n,
+                               const AdamArgs& a, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int th = 256;
+  adam_sigmoid_kernel<<<static_cast<unsigned>((n + th - 1) / th), th, 0, s>>>(theta, h, dl_dh, m, v, n, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_psnr(const float* I, const float* tau, double* out, int W, int T, hipStream_t s) {
+  if (W <= 0) return hipSuccess;
+  psnr_kernel<<<W, kLossThreads, 0, s>>>(I, tau, out, T);
   return hipGetLastError();
 }
 

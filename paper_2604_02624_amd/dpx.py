@@ -88,6 +88,11 @@ def load_library(path: str = LIB_PATH):
     lib.dpx_plan_variant.restype = ctypes.c_int
     lib.dpx_plan_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     lib.dpx_plan_schedule.restype = ctypes.c_int
+    lib.dpx_psnr.argtypes = [vp, vp, vp, vp, vp]
+    lib.dpx_psnr.restype = ctypes.c_int
+    d64 = ctypes.c_double
+    lib.dpx_adam_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, i32, d64, d64, d64, d64, d64, vp]
+    lib.dpx_adam_step.restype = ctypes.c_int
     lib.dpx_timing_enable.argtypes = [vp, i32]
     lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -280,6 +285,18 @@ class Plan:
                                            _ptr(dl_di), _stream(stream)))
         return loss_out, dl_di
 
+    def psnr(self, intensity, target, out=None, stream=None):
+        """Per-wavelength PSNR (dB) of the intensities against the targets, designs in order."""
+        import torch
+        self._check_dev(intensity, self.img_count, torch.float32, "intensity")
+        self._check_dev(target, self.img_count, torch.float32, "target")
+        W = sum(d["n_wl"] for d in self.designs)
+        if out is None:
+            out = torch.empty(W, dtype=torch.float64, device=intensity.device)
+        self._check_dev(out, W, torch.float64, "psnr")
+        _check(self.lib, self.lib.dpx_psnr(self._h, _ptr(intensity), _ptr(target), _ptr(out), _stream(stream)))
+        return out
+
     def backward(self, h, u_in, dl_di, out=None, stream=None):
         import torch
         self._check_dev(h, self.h_count, torch.float32, "h")
@@ -351,3 +368,16 @@ def dpx_intensity(h, plan: Plan, u_in=None):
     if _DpxFunction is None:
         _DpxFunction = _autograd_function()
     return _DpxFunction.apply(h, plan, u_in)
+
+
+def adam_step(theta, h, dl_dh, m, v, step, h_max, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    """One Adam step on theta with h = h_max sigmoid(theta) (dpx_adam_step); all tensors are
+    float32 device tensors of the same length, updated in place."""
+    import torch
+    lib = load_library()
+    n = theta.numel()
+    for t, name in ((theta, "theta"), (h, "h"), (dl_dh, "dl_dh"), (m, "m"), (v, "v")):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} elements")
+    _check(lib, lib.dpx_adam_step(_ptr(theta), _ptr(h), _ptr(dl_dh), _ptr(m), _ptr(v), n, int(step),
+                                  float(lr), float(b1), float(b2), float(eps), float(h_max), _stream(stream)))

@@ -1,0 +1,109 @@
+"""Training the layer heights on top of the fused path.
+
+Paper Section 4 ("Data preparation and other implementation details"): Adam with the optimizer
+library's default parameters, learning rate 0.001, batches of 128 image-wavelength pairs; Section
+2: per-wavelength output PSNR, and dynamic channel swapping (images re-sorted by PSNR and
+reassigned to the wavelengths from the longest down, then fine-tuning).
+
+Readings (the paper leaves them open): the wavelengths are split into fixed contiguous batches
+whose order is shuffled every epoch; the heights stay in [0, h_max] through
+h = h_max * sigmoid(theta) with Adam on theta; PSNR is the textbook one on the unit-sum
+normalised images with the target's peak.  Every step of a training step runs in the library:
+dpx_forward, dpx_loss, dpx_backward on the batch's plan and dpx_adam_step on the device arrays.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import dpx
+from . import workloads as wk
+
+
+def channel_swap_order(psnr_per_wl, wl) -> np.ndarray:
+    """src with new_target[w] = old_target[src[w]]: the images sorted by PSNR (highest first)
+    go to the wavelengths sorted from the longest down."""
+    psnr_per_wl = np.asarray(psnr_per_wl, np.float64)
+    images = sorted(range(len(psnr_per_wl)), key=lambda i: (-psnr_per_wl[i], i))
+    lengths = sorted(range(len(wl)), key=lambda i: (-float(wl[i]), i))
+    src = np.empty(len(wl), dtype=np.int64)
+    for image, w in zip(images, lengths):
+        src[w] = image
+    return src
+
+
+class Trainer:
+    """Adam training of one design's heights over its wavelengths in batches of `batch`."""
+
+    def __init__(self, design: dict, targets: np.ndarray, h_max: float, theta0: np.ndarray | None = None,
+                 batch: int = 128, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8,
+                 u_in: np.ndarray | None = None, plan_opts: dict | None = None):
+        import torch
+        self.torch = torch
+        self.design = design
+        self.h_max = float(h_max)
+        self.lr, self.b1, self.b2, self.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
+        K, N, W = design["layers"], design["n"], design["n_wl"]
+        self.groups = [np.arange(i, min(i + batch, W)) for i in range(0, W, batch)]
+        self.plans = [dpx.Plan([wk.subset_wavelengths(design, g)], **(plan_opts or {})) for g in self.groups]
+        theta = np.zeros((K, N, N), np.float32) if theta0 is None else np.asarray(theta0, np.float32)
+        # initial heights from theta (set-up, host): h = h_max sigmoid(theta) in single precision
+        h0 = (np.float32(self.h_max) / (np.float32(1) + np.exp(-theta, dtype=np.float32))).astype(np.float32)
+        self.theta = torch.as_tensor(theta.reshape(-1)).cuda()
+        self.h = torch.as_tensor(h0.reshape(-1)).cuda()
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.u = None
+        if u_in is not None:
+            self.u = torch.view_as_real(torch.as_tensor(np.asarray(u_in, np.complex64))).reshape(-1).cuda()
+        self.step_count = 0
+        self.set_targets(targets)
+        T = self.plans[0].layouts[0]["target_side"]
+        self._I = [torch.empty(len(g) * T * T, device="cuda") for g in self.groups]
+        self._g = [torch.empty(len(g) * T * T, device="cuda") for g in self.groups]
+        self._dh = torch.empty_like(self.theta)
+
+    def set_targets(self, targets: np.ndarray):
+        self.targets = np.ascontiguousarray(targets, np.float32)
+        self.tau = [p.pack_images([self.targets[g]]) for p, g in zip(self.plans, self.groups)]
+
+    def train_step(self, group: int):
+        """Forward, loss, adjoint on one batch, then one Adam step; returns the batch loss as a
+        device scalar (no synchronisation)."""
+        p = self.plans[group]
+        p.forward(self.h, self.u, self._I[group])
+        L, g = p.loss(self._I[group], self.tau[group], dl_di=self._g[group])
+        p.backward(self.h, self.u, g, self._dh)
+        self.step_count += 1
+        dpx.adam_step(self.theta, self.h, self._dh, self.m, self.v, self.step_count, self.h_max,
+                      lr=self.lr, b1=self.b1, b2=self.b2, eps=self.eps)
+        return L
+
+    def epoch(self, rng: np.random.Generator) -> float:
+        """Every batch once, in a shuffled order; returns the mean batch loss."""
+        losses = [self.train_step(int(gi)) for gi in rng.permutation(len(self.groups))]
+        return float(self.torch.cat(losses).mean().cpu())
+
+    def evaluate(self) -> np.ndarray:
+        """Per-wavelength PSNR (dB) of the current heights, in wavelength order."""
+        out = []
+        for p, gi in zip(self.plans, range(len(self.groups))):
+            I = p.forward(self.h, self.u, self._I[gi])
+            out.append(p.psnr(I, self.tau[gi]))
+        return self.torch.cat(out).cpu().numpy()
+
+    def swap_channels(self, psnr_per_wl=None) -> np.ndarray:
+        """Dynamic channel swapping: reassign the targets by PSNR to the wavelengths from the
+        longest down; returns the permutation applied (new target w = old target src[w])."""
+        if psnr_per_wl is None:
+            psnr_per_wl = self.evaluate()
+        src = channel_swap_order(psnr_per_wl, self.design["wl"])
+        self.set_targets(self.targets[src])
+        return src
+
+    def heights(self) -> np.ndarray:
+        d = self.design
+        return self.h.cpu().numpy().reshape(d["layers"], d["n"], d["n"])
+
+    def close(self):
+        for p in self.plans:
+            p.close()

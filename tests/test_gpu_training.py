@@ -1,0 +1,114 @@
+"""Training support on the GPU against the oracle: the fused Adam step on the heights'
+unconstrained variable, the per-wavelength PSNR, and a few training steps of a small design
+(batches of wavelengths, shuffled order) compared step by step with the same loop driven by
+the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import dpx_oracle as o
+from paper_2604_02624_amd import workloads as wk
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2604_02624_amd import dpx
+    dpx.load_library()
+    return torch
+
+
+def test_adam_step_matches_oracle(torch_dev):
+    say("fused Adam step on theta (h = h_max sigmoid(theta)) vs the FP64 oracle, 4 steps")
+    from paper_2604_02624_amd import dpx
+    torch = torch_dev
+    rng = np.random.default_rng(41)
+    n = 10007
+    h_max = 1.17e-6
+    th = torch.as_tensor(rng.standard_normal(n).astype(np.float32)).cuda()
+    h = torch.empty_like(th)
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    for step in range(1, 5):
+        # gradients over seven decades, some below the eps of the step
+        g = (rng.standard_normal(n) * 10.0 ** rng.uniform(-3, 4, n)).astype(np.float32)
+        prev = [x.cpu().numpy().astype(np.float64) for x in (th, m, v)]
+        dpx.adam_step(th, h, torch.as_tensor(g).cuda(), m, v, step, h_max)
+        t_ref, h_ref, m_ref, v_ref = o.adam_sigmoid_step(prev[0], g.astype(np.float64), prev[1], prev[2],
+                                                         step, h_max)
+        # Single precision, u = 2^-24.  The chain gradient g = dL/dh h_max s (1 - s) carries about
+        # seven roundings (expf within 2 ulp, the add, square, divide and products), so
+        # |dg| <= 7u |g|.  m = b1 m + (1 - b1) g can cancel: its error is bounded by the size of
+        # the terms summed, 16u (b1 |m| + (1 - b1) |g|).  v sums positive terms: 2 * 7u + 3u
+        # relative, bounded by 24u.  theta moves by at most about lr per step: 1e-6 absolute.
+        u = 2.0 ** -24
+        s = o.sigmoid(prev[0])
+        gc = np.abs(g.astype(np.float64) * h_max * s * (1.0 - s))
+        m_scale = 0.9 * np.abs(prev[1]) + 0.1 * gc
+        np.testing.assert_allclose(th.cpu().numpy(), t_ref, rtol=0, atol=1e-6)
+        np.testing.assert_allclose(h.cpu().numpy(), h_ref, rtol=2e-6, atol=0)
+        assert np.all(np.abs(m.cpu().numpy() - m_ref) <= 16 * u * m_scale)
+        np.testing.assert_allclose(v.cpu().numpy(), v_ref, rtol=24 * u, atol=0)
+    with pytest.raises(dpx.DpxError):
+        dpx.adam_step(th, h, torch.zeros_like(th), m, v, 0, h_max)
+
+
+def test_psnr_matches_oracle(torch_dev):
+    say("per-wavelength PSNR on two designs with different target sizes vs the oracle")
+    from paper_2604_02624_amd import dpx
+    torch = torch_dev
+    rng = np.random.default_rng(9)
+    wl = np.array([500e-9, 600e-9, 700e-9])
+    d1 = wk.make_design(n=64, layers=2, wl=wl, n_mat=1.5, dx=300e-9, z=[9e-6, 9e-6], fov=32, pad=2)
+    d2 = wk.make_design(n=32, layers=1, wl=wl[:2], n_mat=1.5, dx=300e-9, z=[5e-6], fov=16, bin_=2, pad=2)
+    plan = dpx.Plan([d1, d2])
+    taus = [rng.random((3, 32, 32)).astype(np.float32), rng.random((2, 8, 8)).astype(np.float32)]
+    Is = [(t * (1 + 0.01 * rng.standard_normal(t.shape))).astype(np.float32) for t in taus]
+    Is[0][1] = taus[0][1]   # identical images: +inf
+    got = plan.psnr(plan.pack_images(Is), plan.pack_images(taus)).cpu().numpy()
+    ref = np.concatenate([o.psnr(I, t) for I, t in zip(Is, taus)])
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(got), fin)
+    np.testing.assert_allclose(got[fin], ref[fin], rtol=1e-12)
+
+
+def test_training_steps_match_oracle_loop(torch_dev):
+    say("six Adam steps of the small design in batches of 3 wavelengths vs the oracle-driven loop")
+    from paper_2604_02624_amd import train
+    w = wk.make_workload(2)
+    d, tau = w["designs"][0], w["targets"][0]
+    h_max = 1.24e-6
+    rng = np.random.default_rng(4)
+    theta0 = (0.5 * rng.standard_normal((d["layers"], d["n"], d["n"]))).astype(np.float32)
+    tr = train.Trainer(d, tau, h_max, theta0=theta0, batch=3, lr=1e-2)
+    order = [0, 1, 1, 0, 1, 0]
+    # oracle loop, FP64, same batches, same order
+    t_ref = theta0.astype(np.float64)
+    m_ref = np.zeros_like(t_ref)
+    v_ref = np.zeros_like(t_ref)
+    h_ref = (np.float32(h_max) / (np.float32(1) + np.exp(-theta0, dtype=np.float32))).astype(np.float64)
+    for step, gi in enumerate(order, start=1):
+        L_gpu = float(tr.train_step(gi).cpu())
+        sub = wk.subset_wavelengths(d, tr.groups[gi])
+        I = o.forward(sub, h_ref.astype(np.float32), None, "fft")
+        L_ref, g_ref, _ = o.loss(I, tau[tr.groups[gi]])
+        dh = o.grad(sub, h_ref.astype(np.float32), None, g_ref, "fft")
+        t_ref, h_ref, m_ref, v_ref = o.adam_sigmoid_step(t_ref, dh, m_ref, v_ref, step, h_max, lr=1e-2)
+        say(f"step {step} batch {gi}: loss gpu {L_gpu:.6e} oracle {L_ref:.6e}")
+        assert abs(L_gpu - L_ref) <= 1e-4 * L_ref
+    th = tr.theta.cpu().numpy().reshape(t_ref.shape)
+    rel = np.linalg.norm(th - t_ref) / np.linalg.norm(t_ref - theta0)
+    say(f"theta after 6 steps: relative difference {rel:.2e} of the distance travelled")
+    assert rel <= 2e-2
+    ps = tr.evaluate()
+    assert ps.shape == (d["n_wl"],) and np.isfinite(ps).all()
+    src = tr.swap_channels(ps)
+    assert sorted(src.tolist()) == list(range(d["n_wl"]))
+    tr.close()
