@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--reps", type=int, default=10,
                     help="single steps and forward calls timed one by one after the timed region "
                          "(median, p10, p90); 0 skips them")
+    ap.add_argument("--train-epochs", type=int, default=1,
+                    help="timed training epochs (128-wavelength batches + Adam) after the step; 0 skips")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -295,6 +297,33 @@ def main():
         extra["device_copy_gbs"] = round(2 * (1 << 30) / (pick(cms, 0.5) / 1e3) / 1e9, 1)
         del src, dst
         log(f"[bench] spread of {args.reps} steps, forward-only and copy bandwidth done")
+    # training: the same design in minibatches of 128 wavelengths, one Adam step per batch
+    # (forward, loss, adjoint and the update on theta), batches in shuffled order
+    if args.train_epochs > 0 and len(designs) == 1:
+        from paper_2604_02624_amd import train
+        d0 = designs[0]
+        hm = d0["h_max"]
+        x = np.clip(w["h"][0] / hm, 1e-4, 1 - 1e-4)
+        tr = train.Trainer(d0, w["targets"][0], hm, theta0=np.log(x / (1 - x)).astype(np.float32),
+                           batch=128, plan_opts=dict(streams=args.streams))
+        trng = np.random.default_rng(0)
+        tr.epoch(trng)
+        log("[bench] training warm-up epoch done")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        tl = [tr.epoch(trng) for _ in range(args.train_epochs)]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ep_ms = e0.elapsed_time(e1) / args.train_epochs
+        nb = len(tr.groups)
+        extra["training"] = dict(
+            value=round(props / (ep_ms / 1e3), 1), unit=UNIT + " (training epoch)", batch=128,
+            batches_per_epoch=nb, epochs=args.train_epochs, ms_per_epoch=round(ep_ms, 3),
+            ms_per_batch=round(ep_ms / nb, 3), vs_full_batch_step=round(ep_ms / ms_step, 3),
+            mean_loss=tl[-1], workspace_bytes=tr.workspace_bytes())
+        tr.close()
+        log(f"[bench] {args.train_epochs} timed training epoch(s) done: {ep_ms:.1f} ms each")
     # sanity: the loss is finite
     Lh = L.cpu().numpy()
     if not np.isfinite(Lh).all():

@@ -192,6 +192,20 @@ dpx_status dpx_plan_destroy(dpx_plan* plan);
 /* Packed-buffer offsets of design `design` (0 <= design < n_designs). */
 dpx_status dpx_plan_layout(const dpx_plan* plan, int32_t design, dpx_layout* out);
 
+/* Replaces the wavelengths of design `design` (paper Section 2: Eq. 1's material index and
+ * extinction and Eq. 4's transfer-function radius are all per wavelength and are recomputed from
+ * these, in double precision on the host).  Minibatch training (Section 4) and sweeps of probe
+ * wavelengths reuse one plan and its workspace this way.
+ *   wl, n_mat  [n_wl] (host, read, not retained): wavelengths in metres and material indices
+ *   kappa      [n_wl] extinction coefficients (host) or NULL for zero
+ *   n_wl       must equal the design's wavelength count at creation
+ * Layer heights, gaps, grid, field of view and workspace are unchanged.  Blocks the host until
+ * the device is idle (queued passes read the old table), then uploads the table and rebuilds
+ * any transfer tables.  Errors: DPX_E_ARG for a bad index, a different count or a value that
+ * dpx_plan_create would reject (the plan is then unchanged); DPX_E_DEVICE for a failed copy. */
+dpx_status dpx_plan_set_wavelengths(dpx_plan* plan, int32_t design, const double* wl,
+                                    const double* n_mat, const double* kappa, int32_t n_wl);
+
 /* Totals over all designs: h floats, u_in complex elements, image floats. */
 dpx_status dpx_plan_sizes(const dpx_plan* plan, int64_t* h_count, int64_t* u_count,
                           int64_t* img_count);

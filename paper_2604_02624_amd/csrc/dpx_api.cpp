@@ -149,9 +149,26 @@ struct dpx_plan {
   const float* last_u = nullptr;
 };
 
+#define DPX_TRY(expr)                   \
+  do {                                  \
+    dpx_status s_ = (expr);             \
+    if (s_ != DPX_OK) return s_;        \
+  } while (0)
+
 namespace {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+dpx_status check_wavelengths(int i, const double* wl, const double* n_mat, const double* kappa, int n) {
+  if (!wl || !n_mat) return fail(DPX_E_ARG, "design %d: wl, n_mat and z are required", i);
+  for (int w = 0; w < n; ++w) {
+    if (!finite_pos(wl[w])) return fail(DPX_E_ARG, "design %d: wl[%d] must be > 0", i, w);
+    if (!std::isfinite(n_mat[w])) return fail(DPX_E_ARG, "design %d: n_mat[%d] not finite", i, w);
+    if (kappa && !(std::isfinite(kappa[w]) && kappa[w] >= 0.0))
+      return fail(DPX_E_ARG, "design %d: kappa[%d] must be finite and >= 0", i, w);
+  }
+  return DPX_OK;
+}
 
 dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
   if (!ds) return fail(DPX_E_ARG, "designs is NULL");
@@ -181,13 +198,8 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
     if (d.pad != 1 && d.pad != 2) return fail(DPX_E_ARG, "design %d: pad must be 1 or 2", i);
     if (!finite_pos(d.dx)) return fail(DPX_E_ARG, "design %d: dx must be finite and > 0", i);
     if (!finite_pos(d.n_medium)) return fail(DPX_E_ARG, "design %d: n_medium must be > 0", i);
-    if (!d.wl || !d.n_mat || !d.z) return fail(DPX_E_ARG, "design %d: wl, n_mat and z are required", i);
-    for (int w = 0; w < d.n_wl; ++w) {
-      if (!finite_pos(d.wl[w])) return fail(DPX_E_ARG, "design %d: wl[%d] must be > 0", i, w);
-      if (!std::isfinite(d.n_mat[w])) return fail(DPX_E_ARG, "design %d: n_mat[%d] not finite", i, w);
-      if (d.kappa && !(std::isfinite(d.kappa[w]) && d.kappa[w] >= 0.0))
-        return fail(DPX_E_ARG, "design %d: kappa[%d] must be finite and >= 0", i, w);
-    }
+    if (!d.z) return fail(DPX_E_ARG, "design %d: wl, n_mat and z are required", i);
+    DPX_TRY(check_wavelengths(i, d.wl, d.n_mat, d.kappa, d.n_wl));
     for (int l = 0; l < d.layers; ++l)
       if (!(std::isfinite(d.z[l]) && d.z[l] >= 0.0))
         return fail(DPX_E_ARG, "design %d: z[%d] must be finite and >= 0", i, l);
@@ -342,12 +354,6 @@ dpx_status sticky_check() {
   }
   return DPX_OK;
 }
-
-#define DPX_TRY(expr)                   \
-  do {                                  \
-    dpx_status s_ = (expr);             \
-    if (s_ != DPX_OK) return s_;        \
-  } while (0)
 
 float2* spec_of_lane(const Design& d, int lane) {
   return d.spec + static_cast<int64_t>(lane) * d.wl_chunk * d.N * d.M;
@@ -1103,6 +1109,38 @@ dpx_status dpx_plan_query(const dpx_design* ds, int32_t nd, const dpx_opts* opts
   return ok();
 }
 
+namespace {
+
+// Per-wavelength constants of Eq. 1 and Eq. 4 (double precision on the host) to the device
+// table, and the transfer tables rebuilt from them when the plan keeps tables.  Synchronous.
+dpx_status upload_wavelengths(Design& d) {
+  std::vector<WlConst> tab(d.W);
+  const double md = static_cast<double>(d.M) * d.dx;
+  for (int w = 0; w < d.W; ++w) {
+    const double lam = d.wl[w];
+    tab[w].rt = (d.n_mat[w] - d.n_m) / lam;
+    tab[w].ca = kTwoPi * d.kappa[w] / lam;
+    const double r = md * d.n_m / lam;
+    tab[w].q0 = r * r;
+    tab[w].ct = kTwoPi * (d.n_mat[w] - d.n_m) / lam;
+  }
+  if (hipMemcpy(d.d_wl, tab.data(), d.W * sizeof(WlConst), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(DPX_E_DEVICE, "copy of the wavelength table failed");
+  for (int k = 0; k < d.nzslots; ++k) {
+    int l = 0;
+    while (d.zslot[l] != k) ++l;
+    const int64_t hs = d.M / 2 + 1;
+    const hipError_t e = dpx::launch_transfer_table(d.M, d.d_wl, d.W, d.z[l] / (static_cast<double>(d.M) * d.dx),
+                                                    d.htab + static_cast<int64_t>(k) * d.W * hs * hs, nullptr);
+    if (e != hipSuccess) return fail(DPX_E_DEVICE, "transfer table launch failed: %s", hipGetErrorString(e));
+  }
+  if (d.nzslots > 0 && hipDeviceSynchronize() != hipSuccess)
+    return fail(DPX_E_DEVICE, "transfer table build failed");
+  return DPX_OK;
+}
+
+}  // namespace
+
 dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opts, dpx_plan** out) {
   if (!out) return fail(DPX_E_ARG, "out is NULL");
   *out = nullptr;
@@ -1140,17 +1178,6 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     h_off += static_cast<int64_t>(d.K) * d.N * d.N;
     u_off += static_cast<int64_t>(d.N) * d.N;
     img_off += static_cast<int64_t>(d.W) * d.T * d.T;
-    // per-wavelength constants (double precision on the host)
-    std::vector<WlConst> tab(d.W);
-    const double md = static_cast<double>(d.M) * d.dx;
-    for (int w = 0; w < d.W; ++w) {
-      const double lam = d.wl[w];
-      tab[w].rt = (d.n_mat[w] - d.n_m) / lam;
-      tab[w].ca = kTwoPi * d.kappa[w] / lam;
-      const double r = md * d.n_m / lam;
-      tab[w].q0 = r * r;
-      tab[w].ct = kTwoPi * (d.n_mat[w] - d.n_m) / lam;
-    }
     const int64_t nn = static_cast<int64_t>(d.N) * d.N;
     const int ck_w = (o.checkpoint_mode == 1) ? d.lanes * d.wl_chunk : d.W;
     if ((st = dev_alloc(&d.d_wl, d.W * sizeof(WlConst), "wavelength table")) != DPX_OK) break;
@@ -1169,24 +1196,8 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
         break;
       }
     }
-    if (hipMemcpy(d.d_wl, tab.data(), d.W * sizeof(WlConst), hipMemcpyHostToDevice) != hipSuccess) {
-      st = fail(DPX_E_DEVICE, "copy of the wavelength table failed");
-      break;
-    }
     p->bytes += d.bytes;
-    for (int k = 0; k < d.nzslots && st == DPX_OK; ++k) {
-      int l = 0;
-      while (d.zslot[l] != k) ++l;
-      const int64_t hs = d.M / 2 + 1;
-      const hipError_t e = dpx::launch_transfer_table(d.M, d.d_wl, d.W, d.z[l] / (static_cast<double>(d.M) * d.dx),
-                                                      d.htab + static_cast<int64_t>(k) * d.W * hs * hs, nullptr);
-      if (e != hipSuccess) st = fail(DPX_E_DEVICE, "transfer table launch failed: %s", hipGetErrorString(e));
-    }
-    if (st != DPX_OK) break;
-    if (d.nzslots > 0 && hipDeviceSynchronize() != hipSuccess) {
-      st = fail(DPX_E_DEVICE, "transfer table build failed");
-      break;
-    }
+    if ((st = upload_wavelengths(d)) != DPX_OK) break;
     if (!p->twiddles.count(d.M)) {
       std::vector<float2> tw;
       dpx::build_twiddle_table(d.M, tw);
@@ -1336,6 +1347,27 @@ dpx_status dpx_plan_layout(const dpx_plan* p, int32_t i, dpx_layout* out) {
   out->workspace_bytes = d.bytes;
   out->transfer_tables = d.nzslots;
   out->lds_path = d.lds ? 1 : 0;
+  return ok();
+}
+
+dpx_status dpx_plan_set_wavelengths(dpx_plan* p, int32_t i, const double* wl, const double* n_mat,
+                                    const double* kappa, int32_t n_wl) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  if (i < 0 || i >= static_cast<int>(p->designs.size()))
+    return fail(DPX_E_ARG, "design index %d out of range", i);
+  Design& d = p->designs[i];
+  if (n_wl != d.W)
+    return fail(DPX_E_ARG, "design %d: n_wl must stay %d (got %d): the workspace is sized for it", i, d.W, n_wl);
+  DPX_TRY(check_wavelengths(i, wl, n_mat, kappa, n_wl));
+  // every pass reads the table: let work already queued finish before it changes
+  if (hipDeviceSynchronize() != hipSuccess) return fail(DPX_E_DEVICE, "device synchronisation failed");
+  d.wl.assign(wl, wl + n_wl);
+  d.n_mat.assign(n_mat, n_mat + n_wl);
+  if (kappa)
+    d.kappa.assign(kappa, kappa + n_wl);
+  else
+    d.kappa.assign(n_wl, 0.0);
+  DPX_TRY(upload_wavelengths(d));
   return ok();
 }
 

@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH):
     d64 = ctypes.c_double
     lib.dpx_adam_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, i32, d64, d64, d64, d64, d64, vp]
     lib.dpx_adam_step.restype = ctypes.c_int
+    lib.dpx_plan_set_wavelengths.argtypes = [vp, i32, vp, vp, vp, i32]
+    lib.dpx_plan_set_wavelengths.restype = ctypes.c_int
     lib.dpx_timing_enable.argtypes = [vp, i32]
     lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -231,6 +233,19 @@ class Plan:
         v = ctypes.c_int32(0)
         _check(self.lib, self.lib.dpx_plan_schedule(self._h, ctypes.byref(v)))
         return int(v.value)
+
+    def set_wavelengths(self, i: int, wl, n_mat, kappa=None):
+        """Rebind design i to new wavelengths (same count); blocks until the device is idle."""
+        arrs = [None if x is None else np.ascontiguousarray(x, np.float64) for x in (wl, n_mat, kappa)]
+        n = len(arrs[0])
+        if len(arrs[1]) != n or (arrs[2] is not None and len(arrs[2]) != n):
+            raise ValueError("wl, n_mat and kappa must have the same length")
+        ptr = [None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        _check(self.lib, self.lib.dpx_plan_set_wavelengths(self._h, i, ptr[0], ptr[1], ptr[2], n))
+        d = dict(self.designs[i])
+        d["wl"], d["n_mat"] = arrs[0], arrs[1]
+        d["kappa"] = arrs[2]
+        self.designs[i] = d
 
     def layout(self, i: int) -> dict:
         lo = CLayout()

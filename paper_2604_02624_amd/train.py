@@ -10,6 +10,8 @@ whose order is shuffled every epoch; the heights stay in [0, h_max] through
 h = h_max * sigmoid(theta) with Adam on theta; PSNR is the textbook one on the unit-sum
 normalised images with the target's peak.  Every step of a training step runs in the library:
 dpx_forward, dpx_loss, dpx_backward on the batch's plan and dpx_adam_step on the device arrays.
+One plan (one workspace) serves every batch of a size: it is rebound to the batch's wavelengths
+with dpx_plan_set_wavelengths when the batch changes.
 """
 from __future__ import annotations
 
@@ -44,7 +46,12 @@ class Trainer:
         self.lr, self.b1, self.b2, self.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
         K, N, W = design["layers"], design["n"], design["n_wl"]
         self.groups = [np.arange(i, min(i + batch, W)) for i in range(0, W, batch)]
-        self.plans = [dpx.Plan([wk.subset_wavelengths(design, g)], **(plan_opts or {})) for g in self.groups]
+        # one plan per batch size, bound to one batch's wavelengths at a time
+        self._plans, self._bound = {}, {}
+        for gi, g in enumerate(self.groups):
+            if len(g) not in self._plans:
+                self._plans[len(g)] = dpx.Plan([wk.subset_wavelengths(design, g)], **(plan_opts or {}))
+                self._bound[len(g)] = gi
         theta = np.zeros((K, N, N), np.float32) if theta0 is None else np.asarray(theta0, np.float32)
         # initial heights from theta (set-up, host): h = h_max sigmoid(theta) in single precision
         h0 = (np.float32(self.h_max) / (np.float32(1) + np.exp(-theta, dtype=np.float32))).astype(np.float32)
@@ -57,21 +64,33 @@ class Trainer:
             self.u = torch.view_as_real(torch.as_tensor(np.asarray(u_in, np.complex64))).reshape(-1).cuda()
         self.step_count = 0
         self.set_targets(targets)
-        T = self.plans[0].layouts[0]["target_side"]
-        self._I = [torch.empty(len(g) * T * T, device="cuda") for g in self.groups]
-        self._g = [torch.empty(len(g) * T * T, device="cuda") for g in self.groups]
+        T = design["fov"] // design["bin"]
+        self._I = {n: torch.empty(n * T * T, device="cuda") for n in self._plans}
+        self._g = {n: torch.empty(n * T * T, device="cuda") for n in self._plans}
         self._dh = torch.empty_like(self.theta)
 
     def set_targets(self, targets: np.ndarray):
         self.targets = np.ascontiguousarray(targets, np.float32)
-        self.tau = [p.pack_images([self.targets[g]]) for p, g in zip(self.plans, self.groups)]
+        self.tau = [self._plans[len(g)].pack_images([self.targets[g]]) for g in self.groups]
+
+    def plan(self, group: int) -> dpx.Plan:
+        """The plan of this batch's size, bound to the batch's wavelengths (rebinding waits for
+        the device to go idle)."""
+        g = self.groups[group]
+        p = self._plans[len(g)]
+        if self._bound[len(g)] != group:
+            sub = wk.subset_wavelengths(self.design, g)
+            p.set_wavelengths(0, sub["wl"], sub["n_mat"], sub.get("kappa"))
+            self._bound[len(g)] = group
+        return p
 
     def train_step(self, group: int):
         """Forward, loss, adjoint on one batch, then one Adam step; returns the batch loss as a
-        device scalar (no synchronisation)."""
-        p = self.plans[group]
-        p.forward(self.h, self.u, self._I[group])
-        L, g = p.loss(self._I[group], self.tau[group], dl_di=self._g[group])
+        device scalar (no synchronisation beyond a rebinding of the plan)."""
+        p = self.plan(group)
+        n = len(self.groups[group])
+        p.forward(self.h, self.u, self._I[n])
+        L, g = p.loss(self._I[n], self.tau[group], dl_di=self._g[n])
         p.backward(self.h, self.u, g, self._dh)
         self.step_count += 1
         dpx.adam_step(self.theta, self.h, self._dh, self.m, self.v, self.step_count, self.h_max,
@@ -86,8 +105,9 @@ class Trainer:
     def evaluate(self) -> np.ndarray:
         """Per-wavelength PSNR (dB) of the current heights, in wavelength order."""
         out = []
-        for p, gi in zip(self.plans, range(len(self.groups))):
-            I = p.forward(self.h, self.u, self._I[gi])
+        for gi, g in enumerate(self.groups):
+            p = self.plan(gi)
+            I = p.forward(self.h, self.u, self._I[len(g)])
             out.append(p.psnr(I, self.tau[gi]))
         return self.torch.cat(out).cpu().numpy()
 
@@ -100,10 +120,14 @@ class Trainer:
         self.set_targets(self.targets[src])
         return src
 
+    def workspace_bytes(self) -> int:
+        """Device bytes held by the trainer's plans (one per batch size)."""
+        return sum(p.layouts[0]["workspace_bytes"] for p in self._plans.values())
+
     def heights(self) -> np.ndarray:
         d = self.design
         return self.h.cpu().numpy().reshape(d["layers"], d["n"], d["n"])
 
     def close(self):
-        for p in self.plans:
+        for p in self._plans.values():
             p.close()

@@ -98,7 +98,8 @@ def _experiment_pair(cfg: int):
     wl = np.arange(500, 741, 48, dtype=np.float64) * 1e-9
     n_const = 1.5
     d = make_design(n=64, layers=2, wl=wl, n_mat=n_const, dx=0.5 * lam_m, z=40 * lam_m, fov=32)
-    h = uniform_heights(rng(cfg, STREAM_HEIGHTS), 2, 64, lam_m / (n_const - 1.0))
+    d["h_max"] = lam_m / (n_const - 1.0)
+    h = uniform_heights(rng(cfg, STREAM_HEIGHTS), 2, 64, d["h_max"])
     tau = binary_targets(rng(cfg, STREAM_TARGETS), d["n_wl"], 32)
     return d, h, tau
 
@@ -111,6 +112,7 @@ def _visible_band(cfg: int, n: int, layers: int, n_wl: int, t: int, gray: bool, 
     n_mat = cauchy_index(wl)
     h_max = lam_m / (float(cauchy_index(np.array([lam_m]))[0]) - 1.0)
     d = make_design(n=n, layers=layers, wl=wl, n_mat=n_mat, dx=0.5 * lam_m, z=50 * lam_m, fov=t)
+    d["h_max"] = h_max
     h = uniform_heights(rng(cfg, STREAM_HEIGHTS, *extra), layers, n, h_max)
     g = rng(cfg, STREAM_TARGETS, *extra)
     tau = grayscale_targets(g, n_wl, t) if gray else binary_targets(g, n_wl, t)

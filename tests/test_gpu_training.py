@@ -112,3 +112,38 @@ def test_training_steps_match_oracle_loop(torch_dev):
     src = tr.swap_channels(ps)
     assert sorted(src.tolist()) == list(range(d["n_wl"]))
     tr.close()
+
+
+@pytest.mark.parametrize("transfer_table", [0, 2])
+def test_set_wavelengths_matches_fresh_plan(torch_dev, transfer_table):
+    say(f"plan rebound to new wavelengths vs a plan created with them (transfer_table={transfer_table})")
+    from paper_2604_02624_amd import dpx
+    torch = torch_dev
+    w = wk.make_workload(2)
+    d = w["designs"][0]
+    a, b = wk.subset_wavelengths(d, [0, 1, 2]), wk.subset_wavelengths(d, [5, 3, 4])
+    tau = w["targets"][0][[5, 3, 4]]
+    rebound = dpx.Plan([a], transfer_table=transfer_table)
+    fresh = dpx.Plan([b], transfer_table=transfer_table)
+    h = rebound.pack_heights(w["h"])
+    t = rebound.pack_images([tau])
+    rebound.forward(h)   # leave work on the old wavelengths queued before the rebinding
+    rebound.set_wavelengths(0, b["wl"], b["n_mat"], b.get("kappa"))
+    outs = []
+    for p in (rebound, fresh):
+        I = p.forward(h)
+        _, g = p.loss(I, t)
+        outs.append((I.cpu().numpy(), p.backward(h, None, g).cpu().numpy()))
+    # same kernels, same constants: identical bits
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    # rejected arguments leave the plan as it was
+    with pytest.raises(dpx.DpxError):
+        rebound.set_wavelengths(0, b["wl"][:2], b["n_mat"][:2])
+    with pytest.raises(dpx.DpxError):
+        rebound.set_wavelengths(0, -b["wl"], b["n_mat"])
+    with pytest.raises(dpx.DpxError):
+        rebound.set_wavelengths(1, b["wl"], b["n_mat"])
+    assert np.array_equal(rebound.forward(h).cpu().numpy(), outs[1][0])
+    rebound.close()
+    fresh.close()
