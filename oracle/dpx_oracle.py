@@ -40,6 +40,11 @@ Readings of the paper used here (each also listed with the design notes):
   multiplies by dx^2 so that it approximates the continuous integral.  The
   angular spectrum needs none (unitary DFT pair).
 * The field outside the N x N layer aperture is dropped after every gap.
+* Misalignment (Section 2, the "vaccination" against lateral and axial
+  displacements): gap l may be lengthened by dz_l and may translate the field
+  it delivers by (sx_l, sy_l), a factor exp(-j 2 pi (fx sx + fy sy)) on H.
+  Layer offsets D_l map to gap translations D_l - D_(l+1) with the output
+  plane fixed; the input field moves with the first layer.
 
 DFT conventions: forward kernel exp(-2 pi j k n / M) with exact integer
 reduction (k n mod M) before the angle is formed, unnormalised; the inverse
@@ -112,13 +117,22 @@ def spatial_frequencies(M: int, dx: float) -> np.ndarray:
     return signed_index(M).astype(np.float64) / (M * dx)
 
 
-def transfer_function(M: int, dx: float, wl: float, n_medium: float, z: float) -> np.ndarray:
-    """H[ky, kx] = exp(+j 2 pi z sqrt(q)) for q = (n_m/lambda)^2 - fx^2 - fy^2 > 0, else 0."""
+def transfer_function(M: int, dx: float, wl: float, n_medium: float, z: float,
+                      shift=(0.0, 0.0)) -> np.ndarray:
+    """H[ky, kx] = exp(+j 2 pi z sqrt(q)) for q = (n_m/lambda)^2 - fx^2 - fy^2 > 0, else 0.
+
+    With shift = (sx, sy) in metres H is multiplied by exp(-j 2 pi (fx sx + fy sy)): the
+    propagated field is translated by (+sx, +sy) (Fourier shift theorem), which is how a
+    lateral misalignment of the following element enters (Section 2, misalignment)."""
     f = spatial_frequencies(M, dx)
     q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
     prop = q > 0.0
     root = np.sqrt(np.where(prop, q, 0.0))
-    return np.where(prop, np.exp(1j * TWO_PI * z * root), 0.0)
+    H = np.where(prop, np.exp(1j * TWO_PI * z * root), 0.0)
+    sx, sy = float(shift[0]), float(shift[1])
+    if sx != 0.0 or sy != 0.0:
+        H = H * np.exp(-1j * TWO_PI * (f[None, :] * sx + f[:, None] * sy))
+    return H
 
 
 def pad_centered(u: np.ndarray, M: int) -> np.ndarray:
@@ -136,12 +150,12 @@ def crop_centered(U: np.ndarray, N: int) -> np.ndarray:
 
 
 def propagate(u: np.ndarray, pad: int, dx: float, wl: float, n_medium: float, z: float,
-              mode: str = "naive", adjoint: bool = False) -> np.ndarray:
+              mode: str = "naive", adjoint: bool = False, shift=(0.0, 0.0)) -> np.ndarray:
     """One gap: pad -> DFT2 -> x H -> IDFT2 -> crop.  ``adjoint`` applies the Hermitian
     adjoint of that linear map, which is the same chain with conj(H)."""
     N = u.shape[-1]
     M = pad * N
-    H = transfer_function(M, dx, wl, n_medium, z)
+    H = transfer_function(M, dx, wl, n_medium, z, shift)
     if adjoint:
         H = np.conj(H)
     V = idft2(H * dft2(pad_centered(u, M), mode), mode)
@@ -168,6 +182,27 @@ def transmission(h: np.ndarray, wl: float, n_mat: float, kappa: float, n_medium:
 # ------------------------------------------------------------------------------------------
 # Cascade, intensity, loss, gradient.
 # ------------------------------------------------------------------------------------------
+
+def gap(design: dict, l: int):
+    """Gap l (after layer l; the last one ends at the output plane) as (length, (sx, sy)):
+    z_l plus the axial jitter dz_l, and the lateral translation of the field it delivers.
+    The optional design keys dz, shift_x, shift_y hold one value per gap in metres."""
+    def at(key):
+        v = design.get(key)
+        return 0.0 if v is None else float(v[l])
+    return float(design["z"][l]) + at("dz"), (at("shift_x"), at("shift_y"))
+
+
+def gap_shifts_from_layer_offsets(D: np.ndarray) -> np.ndarray:
+    """Lateral offsets D[l] = (Dx, Dy) of layers 0..K-1 (output plane fixed) -> the field
+    translation of every gap.  In the frame of a displaced element its transmission is the
+    undisplaced one and the incoming field appears translated by -D; propagation commutes with
+    translations, so gap l translates by D[l] - D[l+1], with D[K] = 0.  The input field is
+    taken in the frame of layer 0 (the aperture moves with the first layer)."""
+    D = np.asarray(D, np.float64)
+    nxt = np.vstack([D[1:], np.zeros((1, 2))])
+    return D - nxt
+
 
 def _kappa(design, w):
     k = design.get("kappa")
@@ -208,8 +243,8 @@ def forward(design: dict, h: np.ndarray, u_in=None, mode: str = "naive", keep: b
             v = transmission(h64[l], wl, nm, _kappa(design, w), design["n_medium"]) * u
             if keep:
                 vs[i, l] = v
-            u = propagate(v, design["pad"], design["dx"], wl, design["n_medium"],
-                          float(design["z"][l]), mode)
+            z, sh = gap(design, l)
+            u = propagate(v, design["pad"], design["dx"], wl, design["n_medium"], z, mode, shift=sh)
         o = u[fs, fs]
         if keep:
             os_[i] = o
@@ -262,8 +297,9 @@ def grad(design: dict, h: np.ndarray, u_in, dl_di: np.ndarray, mode: str = "naiv
         g = np.zeros((N, N), np.complex128)
         g[fs, fs] = 2.0 * dI * os_[i]
         for l in range(K - 1, -1, -1):
-            g = propagate(g, design["pad"], design["dx"], wl, design["n_medium"],
-                          float(design["z"][l]), mode, adjoint=True)
+            z, sh = gap(design, l)
+            g = propagate(g, design["pad"], design["dx"], wl, design["n_medium"], z, mode,
+                          adjoint=True, shift=sh)
             p = np.conj(g) * vs[i, l]
             dh[l] += -c_t * p.imag - c_a * p.real
             g = np.conj(transmission(h64[l], wl, nm, _kappa(design, w), design["n_medium"])) * g

@@ -5,27 +5,60 @@ import pytest
 
 import tests.test_oracle_pins as pins
 import tests.test_oracle_training as tpins
+import tests.test_oracle_misalignment as mpins
 from oracle import dpx_oracle as o
 
 TWO_PI = 2 * np.pi
 
 
-def _h_sign_flipped(M, dx, wl, n_medium, z):
+def _h_sign_flipped(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
     f = o.spatial_frequencies(M, dx)
     q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
     return np.where(q > 0, np.exp(-1j * TWO_PI * z * np.sqrt(np.maximum(q, 0))), 0)
 
 
-def _h_no_cut(M, dx, wl, n_medium, z):
+def _h_no_cut(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
     f = o.spatial_frequencies(M, dx)
     q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
     return np.exp(1j * TWO_PI * z * np.sqrt(q.astype(complex)))
 
 
-def _h_axes_scaled(M, dx, wl, n_medium, z):
+def _h_axes_scaled(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
     f = o.spatial_frequencies(M, dx)
     q = (n_medium / wl) ** 2 - f[None, :] ** 2 - 0.5 * f[:, None] ** 2
     return np.where(q > 0, np.exp(1j * TWO_PI * z * np.sqrt(np.maximum(q, 0))), 0)
+
+
+_orig_transfer = o.transfer_function
+
+
+def _ramp_mutant(ramp):
+    """A transfer function whose shift ramp is computed by ``ramp(f, sx, sy)``."""
+    def H(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
+        f = o.spatial_frequencies(M, dx)
+        return _orig_transfer(M, dx, wl, n_medium, z) * ramp(f, M, dx, float(shift[0]), float(shift[1]))
+    return H
+
+
+_h_ramp_sign_flipped = _ramp_mutant(
+    lambda f, M, dx, sx, sy: np.exp(+1j * TWO_PI * (f[None, :] * sx + f[:, None] * sy)))
+_h_ramp_sign_flipped.__name__ = "_h_ramp_sign_flipped"
+_h_ramp_axes_swapped = _ramp_mutant(
+    lambda f, M, dx, sx, sy: np.exp(-1j * TWO_PI * (f[:, None] * sx + f[None, :] * sy)))
+_h_ramp_axes_swapped.__name__ = "_h_ramp_axes_swapped"
+# frequency in cycles per sample (k/M) times a shift left in metres
+_h_ramp_index_units = _ramp_mutant(
+    lambda f, M, dx, sx, sy: np.exp(-1j * TWO_PI * (f[None, :] * dx * sx + f[:, None] * dx * sy)))
+_h_ramp_index_units.__name__ = "_h_ramp_index_units"
+
+
+def _gap_shifts_reversed(D):
+    D = np.asarray(D, float)
+    return np.vstack([D[1:], np.zeros((1, 2))]) - D
+
+
+def _gap_shifts_absolute(D):
+    return np.asarray(D, float).copy()
 
 
 def _idft_no_norm(V, mode="naive"):
@@ -94,6 +127,11 @@ def _swap_shortest_first(ps, wl):
     return src
 
 CASES = [
+    ("transfer_function", _h_ramp_sign_flipped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
+    ("transfer_function", _h_ramp_axes_swapped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
+    ("transfer_function", _h_ramp_index_units, [mpins.test_subpixel_shift_moves_the_gaussian_centroid_by_the_shift]),
+    ("gap_shifts_from_layer_offsets", _gap_shifts_reversed, [mpins.test_layer_offsets_match_a_physically_displaced_stack]),
+    ("gap_shifts_from_layer_offsets", _gap_shifts_absolute, [mpins.test_layer_offsets_match_a_physically_displaced_stack]),
     ("transfer_function", _h_sign_flipped, [pins.test_tilted_plane_wave, (3, 0)]),
     ("transfer_function", _h_no_cut, [pins.test_evanescent_wave_is_cut_even_at_short_range]),
     ("transfer_function", _h_axes_scaled, [pins.test_tilted_plane_wave, (0, 5)]),
