@@ -206,6 +206,24 @@ dpx_status dpx_plan_layout(const dpx_plan* plan, int32_t design, dpx_layout* out
 dpx_status dpx_plan_set_wavelengths(dpx_plan* plan, int32_t design, const double* wl,
                                     const double* n_mat, const double* kappa, int32_t n_wl);
 
+/* Misalignment of design `design` (paper Section 2, robustness to lateral and axial
+ * displacements and the training against them): gap l (after layer l; the last one ends at the
+ * output plane) is lengthened by dz[l] and translates the field it delivers by
+ * (shift_x[l], shift_y[l]).  The translation is the factor exp(-j 2 pi (fx sx + fy sy)) on the
+ * gap's transfer function, so it costs no extra memory traffic; it is circular over the padded
+ * M x M window.  A layer displaced laterally by D_l maps to gap translations D_l - D_(l+1) and an
+ * axial displacement to dz_l = Dz_(l+1) - Dz_l, with the output plane fixed (D_K = 0).
+ *   dz, shift_x, shift_y  [n_gaps] metres (host, read, not retained), each may be NULL for zeros
+ *   n_gaps                must equal the design's layer count
+ * Takes effect for calls issued after it returns (the values travel as kernel arguments); a
+ * plan with use_graph drops its captured graphs, after waiting for the device.  Forward and
+ * backward must see the same misalignment.  Errors: DPX_E_ARG for a bad index or count, a
+ * non-finite value or a negative gap; DPX_E_UNSUPPORTED for a non-zero misalignment on a design
+ * that runs the grouped schedule, the LDS-resident path or transfer tables, or a lateral one
+ * with the matrix-core column variant.  On error the plan is unchanged. */
+dpx_status dpx_plan_set_misalignment(dpx_plan* plan, int32_t design, const double* dz,
+                                     const double* shift_x, const double* shift_y, int32_t n_gaps);
+
 /* Totals over all designs: h floats, u_in complex elements, image floats. */
 dpx_status dpx_plan_sizes(const dpx_plan* plan, int64_t* h_count, int64_t* u_count,
                           int64_t* img_count);

@@ -52,6 +52,7 @@ struct Design {
   int N, M, K, W, F, b, T, pad;
   double dx, n_m;
   std::vector<double> wl, n_mat, kappa, z;
+  std::vector<double> dz, sx, sy;  // per gap: axial jitter, lateral translation (metres)
   int64_t h_off, u_off, img_off;
   // launch geometry
   int wl_chunk;      // wavelengths per chunk (spec buffer depth per lane)
@@ -459,7 +460,10 @@ ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0
   c.spec = spec_of_lane(d, lane);
   c.wl = d.d_wl;
   c.tw = p->twiddles.at(d.M);
-  c.zrev = d.z[layer] / (static_cast<double>(d.M) * d.dx);
+  const double md = static_cast<double>(d.M) * d.dx;
+  c.zrev = (d.z[layer] + d.dz[layer]) / md;
+  c.sx = d.sx[layer] / md;
+  c.sy = d.sy[layer] / md;
   c.n = d.N;
   c.in_lo = in_lo;
   c.in_hi = in_hi;
@@ -1172,6 +1176,9 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     d.kappa.assign(src.n_wl, 0.0);
     if (src.kappa) d.kappa.assign(src.kappa, src.kappa + src.n_wl);
     d.z.assign(src.z, src.z + src.layers);
+    d.dz.assign(src.layers, 0.0);
+    d.sx.assign(src.layers, 0.0);
+    d.sy.assign(src.layers, 0.0);
     d.h_off = h_off;
     d.u_off = u_off;
     d.img_off = img_off;
@@ -1368,6 +1375,45 @@ dpx_status dpx_plan_set_wavelengths(dpx_plan* p, int32_t i, const double* wl, co
   else
     d.kappa.assign(n_wl, 0.0);
   DPX_TRY(upload_wavelengths(d));
+  return ok();
+}
+
+dpx_status dpx_plan_set_misalignment(dpx_plan* p, int32_t i, const double* dz, const double* shift_x,
+                                     const double* shift_y, int32_t n_gaps) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  if (i < 0 || i >= static_cast<int>(p->designs.size()))
+    return fail(DPX_E_ARG, "design index %d out of range", i);
+  Design& d = p->designs[i];
+  if (n_gaps != d.K) return fail(DPX_E_ARG, "design %d: n_gaps must be %d (got %d)", i, d.K, n_gaps);
+  std::vector<double> nz(d.K, 0.0), nx(d.K, 0.0), ny(d.K, 0.0);
+  bool any = false, lateral = false;
+  for (int l = 0; l < d.K; ++l) {
+    if (dz) nz[l] = dz[l];
+    if (shift_x) nx[l] = shift_x[l];
+    if (shift_y) ny[l] = shift_y[l];
+    if (!(std::isfinite(nz[l]) && std::isfinite(nx[l]) && std::isfinite(ny[l])))
+      return fail(DPX_E_ARG, "design %d: misalignment of gap %d is not finite", i, l);
+    if (!(d.z[l] + nz[l] >= 0.0))
+      return fail(DPX_E_ARG, "design %d: gap %d would be negative (z %g + dz %g)", i, l, d.z[l], nz[l]);
+    any = any || nz[l] != 0.0 || nx[l] != 0.0 || ny[l] != 0.0;
+    lateral = lateral || nx[l] != 0.0 || ny[l] != 0.0;
+  }
+  if (any && (p->grouped || d.lds || d.nzslots > 0))
+    return fail(DPX_E_UNSUPPORTED,
+                "design %d: a misalignment needs the per-design schedule with the transfer function "
+                "evaluated in the column pass (no grouped schedule, LDS-resident path or tables)", i);
+  if (lateral && d.col_variant == 4)
+    return fail(DPX_E_UNSUPPORTED, "design %d: the matrix-core column variant has no lateral translation", i);
+  // captured graphs hold the old kernel arguments
+  if (!p->graphs.empty()) {
+    if (hipDeviceSynchronize() != hipSuccess) return fail(DPX_E_DEVICE, "device synchronisation failed");
+    for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    p->graph_order.clear();
+  }
+  d.dz = nz;
+  d.sx = nx;
+  d.sy = ny;
   return ok();
 }
 

@@ -57,6 +57,10 @@ struct ColArgs {
   const WlConst* wl;         // [W] (global w)
   const float2* tw;          // per-stage twiddle table of the transform length
   double zrev;               // z / (M dx): revolutions per unit of sqrt(q)
+  double sx, sy;             // lateral translation of the gap / (M dx): revolutions per signed
+                             // frequency index (0, 0 unless the plan has a misalignment)
+  float2 ystep;              // exp(-i 2 pi P sy), P = rows between a lane's registers (set by
+                             // the launcher of a translated gap)
   int n;
   int in_lo, in_hi;          // rows holding non-zero input (others read as zero)
   int out_lo, out_hi;        // rows whose output is kept

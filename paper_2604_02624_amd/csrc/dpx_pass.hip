@@ -3,6 +3,8 @@
 // source, single-design and grouped, and the matrix-core form) and the transfer table.  The
 // build compiles this file once per supported length, so the kernel templates of the
 // different lengths are instantiated in parallel translation units.
+#include <cmath>
+
 #include "pass_kernels.hpp"
 
 #ifndef DPX_M
@@ -54,8 +56,11 @@ hipError_t row_group_mode(int mode, const GroupArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-// H source of a launch: the table when the arguments carry one, else the variant's evaluation
-int h_mode(int variant, bool table) { return table ? kHTable : (variant >= 2 ? kHMirror : kHEval); }
+// H source of a launch: the table when the arguments carry one, the per-element evaluation
+// with the translation ramp for a translated gap, else the variant's evaluation
+int h_mode(int variant, bool table, bool shifted = false) {
+  return table ? kHTable : shifted ? kHShift : (variant >= 2 ? kHMirror : kHEval);
+}
 
 // every aperture row in and out (the row-range tests compile away)
 bool full_rows(const ColArgs& a) { return a.in_lo == 0 && a.out_lo == 0 && a.in_hi == a.n && a.out_hi == a.n; }
@@ -78,12 +83,20 @@ template <int PAD, int TX>
 hipError_t col_launch_h(int hm, bool conj, const ColArgs& a, int w_count, hipStream_t s) {
   if (hm == kHTable) return col_launch<PAD, TX, kHTable>(conj, a, w_count, s);
   if (hm == kHMirror) return col_launch<PAD, TX, kHMirror>(conj, a, w_count, s);
+  if (hm == kHShift) return col_launch<PAD, TX, kHShift>(conj, a, w_count, s);
   return col_launch<PAD, TX, kHEval>(conj, a, w_count, s);
 }
 
 template <int PAD>
-hipError_t col_variant(int variant, bool conj, const ColArgs& a, int w_count, hipStream_t s) {
-  const int hm = h_mode(variant, a.htab != nullptr);
+hipError_t col_variant(int variant, bool conj, const ColArgs& args, int w_count, hipStream_t s) {
+  const bool shifted = args.sx != 0.0 || args.sy != 0.0;
+  ColArgs a = args;
+  if (shifted) {
+    // ramp step between a lane's registers (rows P apart), the same for every lane
+    const double ph = -2.0 * 3.14159265358979323846 * (static_cast<double>(Geo<M>::P) * a.sy);
+    a.ystep = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
+  }
+  const int hm = h_mode(variant, a.htab != nullptr, shifted);
   if (col_tile_width(M, variant) == 8) return col_launch_h<PAD, 8>(hm, conj, a, w_count, s);
   return col_launch_h<PAD, 16>(hm, conj, a, w_count, s);
 }
@@ -148,6 +161,7 @@ hipError_t DPX_NAME(launch_row_group_)(int pad, int mode, const GroupArgs& g, hi
 
 hipError_t DPX_NAME(launch_col_)(int pad, bool conj, int variant, const ColArgs& a, int w_count, hipStream_t s) {
   if (variant == 4) {
+    if (a.sx != 0.0 || a.sy != 0.0) return hipErrorInvalidValue;  // matrix-core form: no translation
     if (pad == 2) return colgemm_launch<2>(conj, a, w_count, s);
     if (pad == 1) return colgemm_launch<1>(conj, a, w_count, s);
     return hipErrorInvalidValue;

@@ -264,8 +264,9 @@ __device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
 // ------------------------------------------------------------------------------------------
 // Where a column pass takes the transfer function from: evaluated for every element, evaluated
 // for the rows ky <= M/2 and shared with the mirrored rows across lanes, or read from the
-// plan's table.
-constexpr int kHEval = 0, kHMirror = 1, kHTable = 2;
+// plan's table; a translated gap shares the symmetric part like the mirror form and multiplies
+// every element by its own translation ramp.
+constexpr int kHEval = 0, kHMirror = 1, kHTable = 2, kHShift = 3;
 
 // Block (bx, by) of a column pass: column tile bx of gx, wavelength block by.  The blocks of
 // one pass are numbered bx + gx by from a multiple of 16 in launch order.
@@ -302,7 +303,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
   // hidden; without it those registers would not fit next to the full-length transform and
   // the rows go straight to LDS.  Row k of a lane is one buffer load at the lane's 32-bit
   // byte offset plus the scalar offset k P M 8, so no per-row address stays live.
-  constexpr bool PREFETCH = HALF;
+  constexpr bool PREFETCH = HALF && HM != kHShift;
   const int wb = by * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
   const unsigned voff = static_cast<unsigned>((((FULL ? 0 : a.in_lo) + yy) * M + kx0 + cc) * 8);
@@ -377,25 +378,53 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
       }
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], CONJ ? conjf2(hv[t]) : hv[t]);
-    } else if constexpr (HM == kHMirror) {
+    } else if constexpr (HM == kHMirror || HM == kHShift) {
       // H depends on ky^2 only: lane j0 holds ky = j0 + P t, and for t >= E/2 the row M - ky
       // is register E-1-t of lane P - j0 (lane 0 mirrors onto its own register E - t), so
       // each lane evaluates E/2 + 1 rows and fetches the others across lanes.  Streamed so
       // that only two evaluations are live at a time: step u applies row u and the mirrored
       // row E-1-u (whose value lane 0 takes from its own evaluation u+1).
+      //
+      //
+      // A translated gap (kHShift) also multiplies element (kx, ky) by the ramp
+      // exp(-i 2 pi (kx sx + ky sy)) with signed indices: register u holds ky = j0 + P u and
+      // register E-1-u holds ky - M = j0 - P (u + 1), so with A = ramp(kx, j0) and
+      // B = exp(-i 2 pi P sy) their ramps are A B^u and A conj(B)^(u+1), stepped by one complex
+      // product each (A from an FP64 phase; B, the same for every lane, from the launch
+      // arguments; conjugated for the adjoint).
       constexpr int EH = E / 2;
       const int lane = threadIdx.x & 63;
       const int src = ((lane - j0) + ((P - j0) & (P - 1))) << 2;
+      float2 ra{}, rb{}, step{};
+      if constexpr (HM == kHShift) {
+        ra = cis_turns<1>(-(static_cast<double>(kxs) * a.sx + static_cast<double>(j0) * a.sy));
+        step = a.ystep;
+        if constexpr (CONJ) {
+          ra = conjf2(ra);
+          step = conjf2(step);
+        }
+        rb = cmul(ra, conjf2(step));
+      }
       float2 cur = H(j0);
 #pragma unroll
       for (int u = 0; u < EH; ++u) {
         const float2 nxt = H(j0 + P * (u + 1));
-        reg[u] = cmul(reg[u], cur);
+        if constexpr (HM == kHShift) {
+          reg[u] = cmul(reg[u], cmul(cur, ra));
+          ra = cmul(ra, step);
+        } else {
+          reg[u] = cmul(reg[u], cur);
+        }
         float2 m;
         m.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.x)));
         m.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.y)));
         if (j0 == 0) m = nxt;
-        reg[E - 1 - u] = cmul(reg[E - 1 - u], m);
+        if constexpr (HM == kHShift) {
+          reg[E - 1 - u] = cmul(reg[E - 1 - u], cmul(m, rb));
+          rb = cmul(rb, conjf2(step));
+        } else {
+          reg[E - 1 - u] = cmul(reg[E - 1 - u], m);
+        }
         cur = nxt;
       }
     } else {

@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     lib.dpx_adam_step.restype = ctypes.c_int
     lib.dpx_plan_set_wavelengths.argtypes = [vp, i32, vp, vp, vp, i32]
     lib.dpx_plan_set_wavelengths.restype = ctypes.c_int
+    lib.dpx_plan_set_misalignment.argtypes = [vp, i32, vp, vp, vp, i32]
+    lib.dpx_plan_set_misalignment.restype = ctypes.c_int
     lib.dpx_timing_enable.argtypes = [vp, i32]
     lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -203,6 +205,10 @@ class Plan:
                                                  ctypes.byref(ic)))
         self.h_count, self.u_count, self.img_count = hc.value, uc.value, ic.value
         self.layouts = [self.layout(i) for i in range(len(self.designs))]
+        # designs that carry a misalignment (keys dz, shift_x, shift_y) start with it
+        for i, d in enumerate(self.designs):
+            if any(d.get(k) is not None for k in ("dz", "shift_x", "shift_y")):
+                self.set_misalignment(i, d.get("dz"), d.get("shift_x"), d.get("shift_y"))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -246,6 +252,18 @@ class Plan:
         d["wl"], d["n_mat"] = arrs[0], arrs[1]
         d["kappa"] = arrs[2]
         self.designs[i] = d
+
+    def set_misalignment(self, i: int, dz=None, shift_x=None, shift_y=None):
+        """Per-gap axial jitter and lateral translation (metres, one value per layer) of design
+        i for the calls that follow; None means zeros."""
+        # an index out of range goes to the library, which reports it
+        K = self.designs[i]["layers"] if 0 <= i < len(self.designs) else 0
+        arrs = [None if x is None else np.ascontiguousarray(x, np.float64) for x in (dz, shift_x, shift_y)]
+        for a in arrs:
+            if a is not None and K and a.shape != (K,):
+                raise ValueError(f"misalignment arrays need shape ({K},)")
+        ptr = [None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        _check(self.lib, self.lib.dpx_plan_set_misalignment(self._h, i, ptr[0], ptr[1], ptr[2], K))
 
     def layout(self, i: int) -> dict:
         lo = CLayout()

@@ -103,3 +103,15 @@ def test_gradient_with_misalignment_matches_central_differences():
     v = g.standard_normal(h.shape)
     assert abs((dh * v).sum() - o.fd_direction(d, h, None, tau, v, delta, "naive")) \
         < 1e-6 * abs((dh * v).sum())
+
+
+def test_axial_layer_offsets_match_moved_plane_positions():
+    """Gap lengths recomputed from the displaced plane positions (layer l at Z_l + Dz_l, output
+    plane fixed) equal z_l plus the jitter the conversion gives."""
+    z = np.array([6e-6, 5e-6, 8e-6])
+    Dz = np.array([0.3e-6, -0.2e-6, 0.45e-6])
+    Z = np.concatenate([[0.0], np.cumsum(z)])          # layer planes, then the output plane
+    moved = Z + np.append(Dz, 0.0)
+    assert np.allclose(np.diff(moved), z + o.gap_jitter_from_layer_offsets(Dz), rtol=0, atol=1e-20)
+    # every layer moved by the same amount: only the last gap changes, by minus that amount
+    assert np.allclose(o.gap_jitter_from_layer_offsets(np.full(3, 0.1e-6)), [0, 0, -0.1e-6], atol=1e-22)

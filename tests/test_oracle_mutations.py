@@ -61,6 +61,11 @@ def _gap_shifts_absolute(D):
     return np.asarray(D, float).copy()
 
 
+def _gap_jitter_reversed(Dz):
+    Dz = np.asarray(Dz, float)
+    return Dz - np.append(Dz[1:], 0.0)
+
+
 def _idft_no_norm(V, mode="naive"):
     return np.fft.ifft2(V, axes=(-2, -1)) * V.shape[-1]
 
@@ -131,6 +136,7 @@ CASES = [
     ("transfer_function", _h_ramp_axes_swapped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
     ("transfer_function", _h_ramp_index_units, [mpins.test_subpixel_shift_moves_the_gaussian_centroid_by_the_shift]),
     ("gap_shifts_from_layer_offsets", _gap_shifts_reversed, [mpins.test_layer_offsets_match_a_physically_displaced_stack]),
+    ("gap_jitter_from_layer_offsets", _gap_jitter_reversed, [mpins.test_axial_layer_offsets_match_moved_plane_positions]),
     ("gap_shifts_from_layer_offsets", _gap_shifts_absolute, [mpins.test_layer_offsets_match_a_physically_displaced_stack]),
     ("transfer_function", _h_sign_flipped, [pins.test_tilted_plane_wave, (3, 0)]),
     ("transfer_function", _h_no_cut, [pins.test_evanescent_wave_is_cut_even_at_short_range]),
