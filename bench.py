@@ -289,6 +289,20 @@ def main():
                                 p90=round(pick(steps_ms, 0.9), 3), reps=args.reps)
         extra["forward_only"] = dict(value=round(props / (pick(fwd_ms, 0.5) / 1e3), 1),
                                      unit="propagations/s (forward)", ms_median=round(pick(fwd_ms, 0.5), 3))
+        # a misaligned step: every layer displaced by up to +-40 nm laterally and +-200 nm
+        # axially (translated gaps evaluate the transfer function with their ramp)
+        if (len(designs) == 1 and plan.schedule() == 1 and not plan.uses_lds_path()
+                and not plan.has_transfer_tables() and plan.variant(0) != 4):
+            from paper_2604_02624_amd import robustness
+            lat, ax = robustness.draw_layer_offsets(np.random.default_rng(1), designs[0]["layers"],
+                                                    40e-9, 200e-9)
+            plan.set_misalignment(0, *robustness.gap_offsets(lat, ax))
+            step()
+            mis_ms = sorted(timed(step) for _ in range(args.reps))
+            plan.set_misalignment(0)
+            extra["misaligned_step"] = dict(ms_median=round(pick(mis_ms, 0.5), 3),
+                                            vs_aligned=round(pick(mis_ms, 0.5) / pick(steps_ms, 0.5), 3),
+                                            offsets="layers displaced U(+-40 nm) laterally, U(+-200 nm) axially")
         n = (1 << 30) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -11,13 +11,16 @@ h = h_max * sigmoid(theta) with Adam on theta; PSNR is the textbook one on the u
 normalised images with the target's peak.  Every step of a training step runs in the library:
 dpx_forward, dpx_loss, dpx_backward on the batch's plan and dpx_adam_step on the device arrays.
 One plan (one workspace) serves every batch of a size: it is rebound to the batch's wavelengths
-with dpx_plan_set_wavelengths when the batch changes.
+with dpx_plan_set_wavelengths when the batch changes.  With `misalign = (d_xy, d_z)` every step
+draws a new misalignment of the layers (uniform in +-d_xy laterally, +-d_z axially) and trains
+through it ("vaccination", Section 2).
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import dpx
+from . import robustness
 from . import workloads as wk
 
 
@@ -38,7 +41,8 @@ class Trainer:
 
     def __init__(self, design: dict, targets: np.ndarray, h_max: float, theta0: np.ndarray | None = None,
                  batch: int = 128, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8,
-                 u_in: np.ndarray | None = None, plan_opts: dict | None = None):
+                 u_in: np.ndarray | None = None, plan_opts: dict | None = None,
+                 misalign: tuple | None = None, misalign_seed: int = 0):
         import torch
         self.torch = torch
         self.design = design
@@ -63,6 +67,9 @@ class Trainer:
         if u_in is not None:
             self.u = torch.view_as_real(torch.as_tensor(np.asarray(u_in, np.complex64))).reshape(-1).cuda()
         self.step_count = 0
+        self.misalign = misalign
+        self._mis_rng = np.random.default_rng(misalign_seed)
+        self.last_offsets = None
         self.set_targets(targets)
         T = design["fov"] // design["bin"]
         self._I = {n: torch.empty(n * T * T, device="cuda") for n in self._plans}
@@ -89,6 +96,11 @@ class Trainer:
         device scalar (no synchronisation beyond a rebinding of the plan)."""
         p = self.plan(group)
         n = len(self.groups[group])
+        if self.misalign is not None:
+            lateral, axial = robustness.draw_layer_offsets(self._mis_rng, self.design["layers"],
+                                                           *self.misalign)
+            self.last_offsets = (lateral, axial)
+            p.set_misalignment(0, *robustness.gap_offsets(lateral, axial))
         p.forward(self.h, self.u, self._I[n])
         L, g = p.loss(self._I[n], self.tau[group], dl_di=self._g[n])
         p.backward(self.h, self.u, g, self._dh)
@@ -102,13 +114,20 @@ class Trainer:
         losses = [self.train_step(int(gi)) for gi in rng.permutation(len(self.groups))]
         return float(self.torch.cat(losses).mean().cpu())
 
-    def evaluate(self) -> np.ndarray:
-        """Per-wavelength PSNR (dB) of the current heights, in wavelength order."""
+    def evaluate(self, offsets=None) -> np.ndarray:
+        """Per-wavelength PSNR (dB) of the current heights, in wavelength order, aligned or with
+        the layer displacements offsets = (lateral [K, 2], axial [K])."""
+        gaps = (None, None, None) if offsets is None else robustness.gap_offsets(*offsets)
+        for p in self._plans.values():
+            p.set_misalignment(0, *gaps)
         out = []
         for gi, g in enumerate(self.groups):
             p = self.plan(gi)
             I = p.forward(self.h, self.u, self._I[len(g)])
             out.append(p.psnr(I, self.tau[gi]))
+        if offsets is not None:
+            for p in self._plans.values():
+                p.set_misalignment(0)
         return self.torch.cat(out).cpu().numpy()
 
     def swap_channels(self, psnr_per_wl=None) -> np.ndarray:

@@ -147,3 +147,65 @@ def test_set_wavelengths_matches_fresh_plan(torch_dev, transfer_table):
     assert np.array_equal(rebound.forward(h).cpu().numpy(), outs[1][0])
     rebound.close()
     fresh.close()
+
+
+def test_vaccinated_training_matches_oracle_loop(torch_dev):
+    say("four Adam steps with a fresh layer misalignment per step vs the oracle-driven loop")
+    from paper_2604_02624_amd import train
+    w = wk.make_workload(2)
+    d, tau = w["designs"][0], w["targets"][0]
+    h_max = 1.24e-6
+    theta0 = (0.5 * np.random.default_rng(6).standard_normal((d["layers"], d["n"], d["n"]))).astype(np.float32)
+    # misalignments the size of a pixel (310 nm) so that they matter at this grid
+    tr = train.Trainer(d, tau, h_max, theta0=theta0, batch=3, lr=1e-2, misalign=(300e-9, 2e-6),
+                       misalign_seed=17)
+    t_ref = theta0.astype(np.float64)
+    m_ref = np.zeros_like(t_ref)
+    v_ref = np.zeros_like(t_ref)
+    h_ref = (np.float32(h_max) / (np.float32(1) + np.exp(-theta0, dtype=np.float32))).astype(np.float64)
+    for step, gi in enumerate([1, 0, 0, 1], start=1):
+        L_gpu = float(tr.train_step(gi).cpu())
+        lateral, axial = tr.last_offsets
+        s = o.gap_shifts_from_layer_offsets(lateral)
+        sub = dict(wk.subset_wavelengths(d, tr.groups[gi]), shift_x=s[:, 0], shift_y=s[:, 1],
+                   dz=o.gap_jitter_from_layer_offsets(axial))
+        I = o.forward(sub, h_ref.astype(np.float32), None, "fft")
+        L_ref, g_ref, _ = o.loss(I, tau[tr.groups[gi]])
+        dh = o.grad(sub, h_ref.astype(np.float32), None, g_ref, "fft")
+        t_ref, h_ref, m_ref, v_ref = o.adam_sigmoid_step(t_ref, dh, m_ref, v_ref, step, h_max, lr=1e-2)
+        say(f"step {step} batch {gi}: loss gpu {L_gpu:.6e} oracle {L_ref:.6e}")
+        assert abs(L_gpu - L_ref) <= 1e-4 * L_ref
+    th = tr.theta.cpu().numpy().reshape(t_ref.shape)
+    rel = np.linalg.norm(th - t_ref) / np.linalg.norm(t_ref - theta0)
+    say(f"theta after 4 steps: relative difference {rel:.2e} of the distance travelled")
+    assert rel <= 2e-2
+    # evaluation with and without a given misalignment, then training state is aligned again
+    off = (np.full((d["layers"], 2), 310e-9), np.zeros(d["layers"]))
+    ps_mis = tr.evaluate(off)
+    ps = tr.evaluate()
+    assert np.isfinite(ps).all() and np.isfinite(ps_mis).all() and not np.array_equal(ps, ps_mis)
+    tr.close()
+
+
+def test_detuning_sweep_matches_oracle(torch_dev):
+    say("PSNR of 5 detuned probes per channel (+-0.1 channel spacing) vs the oracle")
+    from paper_2604_02624_amd import dpx, robustness
+    wl = np.linspace(450e-9, 750e-9, 6)
+    d = wk.make_design(n=64, layers=2, wl=wl, n_mat=wk.cauchy_index(wl), dx=300e-9, z=[30e-6, 30e-6],
+                       fov=32, pad=2)
+    g = np.random.default_rng(8)
+    h = (g.random((2, 64, 64)) * 1.3e-6).astype(np.float32)
+    tau = g.random((6, 32, 32)).astype(np.float32)
+    plan = dpx.Plan([d])
+    spacing = wl[1] - wl[0]
+    offsets = np.linspace(-0.1, 0.1, 5) * spacing
+    ps = robustness.detuning_psnr(plan, plan.pack_heights([h]), plan.pack_images([tau]), offsets,
+                                  wk.cauchy_index)
+    ref = np.stack([o.psnr(o.forward(dict(d, wl=wl + off, n_mat=wk.cauchy_index(wl + off)), h, None, "fft"), tau)
+                    for off in offsets])
+    say(f"largest PSNR difference {np.abs(ps - ref).max():.2e} dB")
+    assert ps.shape == (5, 6)
+    assert np.abs(ps - ref).max() <= 1e-3
+    # the plan is back on its own wavelengths
+    assert np.array_equal(plan.designs[0]["wl"], wl)
+    plan.close()
