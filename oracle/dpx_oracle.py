@@ -40,6 +40,10 @@ Readings of the paper used here (each also listed with the design notes):
   multiplies by dx^2 so that it approximates the continuous integral.  The
   angular spectrum needs none (unitary DFT pair).
 * The field outside the N x N layer aperture is dropped after every gap.
+* Input plane: the uniform illumination passes the input aperture (u_in) and
+  reaches layer 1 after the optional gap z_in (the Fig. 1 schematic, the
+  input plane being one of the planes connected by diffraction); z_in = 0
+  means u_in is the field at layer 1.
 * Misalignment (Section 2, the "vaccination" against lateral and axial
   displacements): gap l may be lengthened by dz_l and may translate the field
   it delivers by (sx_l, sy_l), a factor exp(-j 2 pi (fx sx + fy sy)) on H.
@@ -204,6 +208,14 @@ def gap_shifts_from_layer_offsets(D: np.ndarray) -> np.ndarray:
     return D - nxt
 
 
+def gap_jitter_from_layer_offsets(Dz: np.ndarray) -> np.ndarray:
+    """Axial offsets Dz[l] of layers 0..K-1 (output plane fixed) -> the change of every gap
+    length: gap l runs from layer l to layer l+1 (or the output plane), so it changes by
+    Dz[l+1] - Dz[l], with Dz[K] = 0."""
+    Dz = np.asarray(Dz, np.float64)
+    return np.append(Dz[1:], 0.0) - Dz
+
+
 def _kappa(design, w):
     k = design.get("kappa")
     return 0.0 if k is None else float(k[w])
@@ -236,9 +248,13 @@ def forward(design: dict, h: np.ndarray, u_in=None, mode: str = "naive", keep: b
     out = np.zeros((len(ws), T, T), dtype=np.float64)
     vs = np.zeros((len(ws), K, N, N), np.complex128) if keep else None
     os_ = np.zeros((len(ws), design["fov"], design["fov"]), np.complex128) if keep else None
+    z_in = float(design.get("z_in") or 0.0)
     for i, w in enumerate(ws):
         wl, nm = float(design["wl"][w]), float(design["n_mat"][w])
         u = u0
+        if z_in > 0.0:
+            # the input plane (u_in, e.g. the illumination aperture) lies z_in before layer 1
+            u = propagate(u0, design["pad"], design["dx"], wl, design["n_medium"], z_in, mode)
         for l in range(K):
             v = transmission(h64[l], wl, nm, _kappa(design, w), design["n_medium"]) * u
             if keep:

@@ -6,6 +6,7 @@ import pytest
 import tests.test_oracle_pins as pins
 import tests.test_oracle_training as tpins
 import tests.test_oracle_misalignment as mpins
+import tests.test_oracle_input_gap as gpins
 from oracle import dpx_oracle as o
 
 TWO_PI = 2 * np.pi
@@ -64,6 +65,13 @@ def _gap_shifts_absolute(D):
 def _gap_jitter_reversed(Dz):
     Dz = np.asarray(Dz, float)
     return Dz - np.append(Dz[1:], 0.0)
+
+
+_orig_forward = o.forward
+
+
+def _forward_without_input_gap(design, *args, **kw):
+    return _orig_forward(dict(design, z_in=0.0), *args, **kw)
 
 
 def _idft_no_norm(V, mode="naive"):
@@ -132,6 +140,7 @@ def _swap_shortest_first(ps, wl):
     return src
 
 CASES = [
+    ("forward", _forward_without_input_gap, [gpins.test_input_gap_equals_a_leading_transparent_layer]),
     ("transfer_function", _h_ramp_sign_flipped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
     ("transfer_function", _h_ramp_axes_swapped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
     ("transfer_function", _h_ramp_index_units, [mpins.test_subpixel_shift_moves_the_gaussian_centroid_by_the_shift]),
