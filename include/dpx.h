@@ -89,6 +89,10 @@ typedef struct dpx_design {
   const double* n_mat;  /* [W] real refractive index n(lambda) of the layer material */
   const double* kappa;  /* [W] extinction coefficient kappa(lambda), or NULL for 0 */
   const double* z;      /* [K] z[l] = gap after layer l (z[K-1]: last layer -> output plane) */
+  double z_in;          /* gap from the input plane (u_in, e.g. the illumination aperture) to
+                           layer 1, metres; 0 = u_in is the field at layer 1 (Fig. 1: the input
+                           plane, the layers and the output plane are connected by diffraction).
+                           A design with z_in > 0 runs the per-design schedule. */
 } dpx_design;
 
 typedef struct dpx_opts {

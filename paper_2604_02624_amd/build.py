@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-ffp-contract=off",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 # transform lengths with their own translation unit of pass kernels (dpx_pass.hip)
-LENGTHS = [64, 96, 128, 192, 256, 384, 512, 1024]
+LENGTHS = [64, 96, 128, 192, 256, 384, 512, 1024, 1600]
 # (source, object name, extra flags); the long-running pass units first
 UNITS = ([("dpx_pass.hip", f"dpx_pass_{m}.o", [f"-DDPX_M={m}"]) for m in sorted(LENGTHS, reverse=True)]
          + [("dpx_kernels.hip", "dpx_kernels.o", []), ("dpx_api.cpp", "dpx_api.o", [])])

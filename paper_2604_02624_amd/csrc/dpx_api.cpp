@@ -53,6 +53,7 @@ struct Design {
   double dx, n_m;
   std::vector<double> wl, n_mat, kappa, z;
   std::vector<double> dz, sx, sy;  // per gap: axial jitter, lateral translation (metres)
+  double z_in = 0.0;               // input plane -> layer 1 (0: u_in is the field at layer 1)
   int64_t h_off, u_off, img_off;
   // launch geometry
   int wl_chunk;      // wavelengths per chunk (spec buffer depth per lane)
@@ -204,6 +205,8 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
     for (int l = 0; l < d.layers; ++l)
       if (!(std::isfinite(d.z[l]) && d.z[l] >= 0.0))
         return fail(DPX_E_ARG, "design %d: z[%d] must be finite and >= 0", i, l);
+    if (!(std::isfinite(d.z_in) && d.z_in >= 0.0))
+      return fail(DPX_E_ARG, "design %d: z_in must be finite and >= 0", i);
     const int M = d.pad * d.n;
     if (o && o->force_variant >= 0 && dpx::fft_size_supported(M) &&
         !dpx::col_variant_supported(M, d.pad, o->force_variant))
@@ -230,6 +233,7 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   d.T = src.fov / src.bin;
   d.dx = src.dx;
   d.n_m = src.n_medium;
+  d.z_in = src.z_in;
   const int P = dpx::row_lanes_per_transform(d.M);
   (void)P;
   d.row_group = dpx::row_rows_per_block(d.M, dpx::ROW_FWD_MID);
@@ -257,6 +261,7 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   // LDS-resident path for short transforms (opts.small_path = 1): every wavelength is one
   // block with one dL/dh slot, the whole design one chunk
   d.lds = o.small_path == 1 && o.checkpoint_mode == 0 && o.streams <= 1 && o.force_variant < 0 &&
+          src.z_in == 0.0 &&
           o.transfer_table != 2 && dpx::lds_path_supported(d.M, d.pad);
   if (d.lds) {
     chunk = d.W;
@@ -460,10 +465,11 @@ ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0
   c.spec = spec_of_lane(d, lane);
   c.wl = d.d_wl;
   c.tw = p->twiddles.at(d.M);
+  // layer -1: the input gap (no misalignment, transfer function evaluated in the pass)
   const double md = static_cast<double>(d.M) * d.dx;
-  c.zrev = (d.z[layer] + d.dz[layer]) / md;
-  c.sx = d.sx[layer] / md;
-  c.sy = d.sy[layer] / md;
+  c.zrev = (layer < 0 ? d.z_in : d.z[layer] + d.dz[layer]) / md;
+  c.sx = layer < 0 ? 0.0 : d.sx[layer] / md;
+  c.sy = layer < 0 ? 0.0 : d.sy[layer] / md;
   c.n = d.N;
   c.in_lo = in_lo;
   c.in_hi = in_hi;
@@ -480,7 +486,7 @@ ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0
   // leaves several blocks per CU
   c.col_wpb = (static_cast<int64_t>(wc) * (d.M / 8) >= 2 * 8192) ? 2 : 1;
   const int64_t hs = d.M / 2 + 1;
-  c.htab = d.htab ? d.htab + static_cast<int64_t>(d.zslot[layer]) * d.W * hs * hs : nullptr;
+  c.htab = (d.htab && layer >= 0) ? d.htab + static_cast<int64_t>(d.zslot[layer]) * d.W * hs * hs : nullptr;
   return c;
 }
 
@@ -517,11 +523,26 @@ dpx_status forward_chunk(dpx_plan* p, const Design& d, const float* h, const flo
   const int fo = (d.N - d.F) / 2;
   RowArgs a = row_args(p, d, w0, wc, lane);
   a.u_in = u_in ? reinterpret_cast<const float2*>(u_in) + d.u_off : nullptr;
-  a.store_ckpt = 1;
   a.layer = 0;
-  a.h = h + h_off_layer(d, 0);
-  DPX_TRY(run_row(p, d, dpx::ROW_FWD_FIRST, a, 0, d.N, s));
-  if (after_first) DPX_HIP(hipEventRecord(after_first, s));
+  if (d.z_in > 0.0) {
+    // input plane: u_in to the spectrum unchanged, across the input gap, then layer 0 as a
+    // middle pass (row inverse transform, transmission, checkpoint, row transform)
+    a.no_layer = 1;
+    a.store_ckpt = 0;
+    a.h = nullptr;
+    DPX_TRY(run_row(p, d, dpx::ROW_FWD_FIRST, a, 0, d.N, s));
+    if (after_first) DPX_HIP(hipEventRecord(after_first, s));
+    DPX_TRY(run_col(p, d, lane, -1, false, w0, wc, 0, d.N, 0, d.N, s));
+    a.no_layer = 0;
+    a.store_ckpt = 1;
+    a.h = h + h_off_layer(d, 0);
+    DPX_TRY(run_row(p, d, dpx::ROW_FWD_MID, a, 0, d.N, s));
+  } else {
+    a.store_ckpt = 1;
+    a.h = h + h_off_layer(d, 0);
+    DPX_TRY(run_row(p, d, dpx::ROW_FWD_FIRST, a, 0, d.N, s));
+    if (after_first) DPX_HIP(hipEventRecord(after_first, s));
+  }
   for (int l = 0; l < d.K; ++l) {
     const bool last = (l == d.K - 1);
     DPX_TRY(run_col(p, d, lane, l, false, w0, wc, 0, d.N, last ? fo : 0, last ? fo + d.F : d.N, s));
@@ -714,7 +735,7 @@ void add_simple_group(std::vector<GroupLaunch>& out, GroupKind kind, const std::
 bool groupable(const dpx_plan* p) {
   if (p->opts.checkpoint_mode != 0) return false;
   for (const auto& d : p->designs)
-    if (d.nchunks != 1 || d.lanes != 1 || d.col_variant > 3) return false;
+    if (d.nchunks != 1 || d.lanes != 1 || d.col_variant > 3 || d.z_in > 0.0) return false;
   return true;
 }
 
@@ -1102,7 +1123,7 @@ dpx_status dpx_plan_query(const dpx_design* ds, int32_t nd, const dpx_opts* opts
     layout_design(ds[i], o, d);
     tot += d.bytes;
     ms[d.M] = 1;
-    groupable_all = groupable_all && d.nchunks == 1 && d.lanes == 1 && d.col_variant <= 3;
+    groupable_all = groupable_all && d.nchunks == 1 && d.lanes == 1 && d.col_variant <= 3 && d.z_in == 0.0;
   }
   if (o.schedule == 2 && !groupable_all)
     return fail(DPX_E_UNSUPPORTED,
@@ -1404,6 +1425,8 @@ dpx_status dpx_plan_set_misalignment(dpx_plan* p, int32_t i, const double* dz, c
                 "evaluated in the column pass (no grouped schedule, LDS-resident path or tables)", i);
   if (lateral && d.col_variant == 4)
     return fail(DPX_E_UNSUPPORTED, "design %d: the matrix-core column variant has no lateral translation", i);
+  if (lateral && !dpx::col_translation_supported(d.M))
+    return fail(DPX_E_UNSUPPORTED, "design %d: no lateral translation at transform length %d", i, d.M);
   // captured graphs hold the old kernel arguments
   if (!p->graphs.empty()) {
     if (hipDeviceSynchronize() != hipSuccess) return fail(DPX_E_DEVICE, "device synchronisation failed");

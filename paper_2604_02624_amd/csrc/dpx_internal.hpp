@@ -31,6 +31,11 @@ enum RowMode : int {
 // Threads per row-pass block: 512 (eight transforms of 1024) where the registers allow two
 // such blocks per CU next to their LDS, 256 for the register-heavy adjoint middle pass.
 constexpr int row_threads_of_mode(int mode) { return mode == ROW_ADJ_MID ? 256 : 512; }
+// Threads of a row-pass block for P lanes per transform: the mode's count when transforms tile
+// a wavefront; three or so whole transforms (about 256 threads) when one spans wavefronts.
+constexpr int row_threads_for(int P, int mode) {
+  return (P <= 64 && 64 % P == 0) ? row_threads_of_mode(mode) : (256 / P) * P;
+}
 
 struct RowArgs {
   float2* spec;              // [wc][N][M] row-transformed planes of the current chunk
@@ -50,6 +55,8 @@ struct RowArgs {
   int ckpt_w_stride;         // wavelengths in one checkpoint layer slab
   int store_ckpt;
   int accumulate;            // dL/dh partials: add to the slot instead of overwriting it
+  int no_layer;              // ROW_FWD_FIRST only: u_in passes unchanged (the input plane before
+                             // an input gap: no transmission, h not read)
 };
 
 struct ColArgs {
@@ -186,7 +193,7 @@ __device__ __forceinline__ int group_task(const GroupArgs& g, int b) {
 }
 
 // Supported transform lengths; the pass launchers of each live in their own translation unit.
-#define DPX_FOR_EACH_M(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
+#define DPX_FOR_EACH_M(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024) X(1600)
 #define DPX_DECLARE_PASS_LAUNCHERS(m)                                                                   \
   hipError_t launch_row_##m(int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,       \
                             hipStream_t s);                                                             \
@@ -222,6 +229,7 @@ bool col_variant_supported(int M, int pad, int variant);
 void build_dft_table(int M, int pad, std::vector<float2>& out);
 extern const char* const kColVariantNames[kColVariants];
 int default_col_variant(int M);
+bool col_translation_supported(int M);  // translated gaps (needs the mirrored H form)
 hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
                       hipStream_t s);
 // fills out[w][|kx|][|ky|] (w < W, |kx|, |ky| <= M/2) with H / M^2 of the gap z = zrev M dx,

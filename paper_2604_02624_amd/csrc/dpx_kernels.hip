@@ -283,8 +283,17 @@ int row_lanes_per_transform(int M) {
 int row_rows_per_block(int M, int mode) {
   const int P = row_lanes_per_transform(M);
   if (P == 0) return 0;
-  return row_threads_of_mode(mode) / P;
+  return row_threads_for(P, mode) / P;
 }
+
+namespace {
+// the lanes of one transform lie in one wavefront (else its LDS exchanges take block barriers,
+// tiles are 4 or 8 columns wide and H has no cross-lane mirrored form)
+bool wave_local(int M) {
+  const int P = row_lanes_per_transform(M);
+  return P > 0 && P <= 64 && 64 % P == 0;
+}
+}  // namespace
 
 // Column-pass variants (0-3 give the same results bit for bit; 4 differs by rounding):
 //   0: 8-column tiles, 1: 16-column tiles, 2: 8-column tiles + mirrored H rows,
@@ -296,16 +305,20 @@ const char* const kColVariantNames[kColVariants] = {"tile8", "tile16", "tile8+mi
                                                     "tile16+mirror", "dft-gemm-mfma"};
 
 // built-in choice when no variant is forced and no autotuning is asked for
-int default_col_variant(int M) { return M >= 512 ? 2 : 3; }
+int default_col_variant(int M) { return !wave_local(M) ? 0 : M >= 512 ? 2 : 3; }
+
+bool col_translation_supported(int M) { return wave_local(M); }
 
 bool col_variant_supported(int M, int pad, int variant) {
   if (variant < 0 || variant >= kColVariants) return false;
   if (variant == 4) return M <= 512 && M % 16 == 0 && (M / pad) % 16 == 0;
+  if (!wave_local(M)) return variant <= 1;
   return true;
 }
 
 int col_tile_width(int M, int variant) {
   const int P = row_lanes_per_transform(M);
+  if (!wave_local(M)) return variant == 0 ? 4 : 8;
   return ((variant == 0 || variant == 2) && 8 * P >= 64) ? 8 : 16;
 }
 

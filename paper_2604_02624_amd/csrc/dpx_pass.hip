@@ -79,11 +79,21 @@ hipError_t col_launch(bool conj, const ColArgs& a, int w_count, hipStream_t s) {
   return hipGetLastError();
 }
 
+// tile widths of the transform variants: 8 / 16 columns, or 4 / 8 when a transform spans
+// wavefronts (blocks stay within 1024 threads)
+constexpr int kTileNarrow = Geo<M>::WAVE_LOCAL ? 8 : 4;
+constexpr int kTileWide = Geo<M>::WAVE_LOCAL ? 16 : 8;
+
 template <int PAD, int TX>
 hipError_t col_launch_h(int hm, bool conj, const ColArgs& a, int w_count, hipStream_t s) {
   if (hm == kHTable) return col_launch<PAD, TX, kHTable>(conj, a, w_count, s);
-  if (hm == kHMirror) return col_launch<PAD, TX, kHMirror>(conj, a, w_count, s);
-  if (hm == kHShift) return col_launch<PAD, TX, kHShift>(conj, a, w_count, s);
+  if constexpr (Geo<M>::WAVE_LOCAL) {
+    if (hm == kHMirror) return col_launch<PAD, TX, kHMirror>(conj, a, w_count, s);
+    if (hm == kHShift) return col_launch<PAD, TX, kHShift>(conj, a, w_count, s);
+  } else {
+    // the mirrored forms exchange H across the lanes of one wavefront
+    if (hm == kHMirror || hm == kHShift) return hipErrorInvalidValue;
+  }
   return col_launch<PAD, TX, kHEval>(conj, a, w_count, s);
 }
 
@@ -97,8 +107,8 @@ hipError_t col_variant(int variant, bool conj, const ColArgs& args, int w_count,
     a.ystep = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
   }
   const int hm = h_mode(variant, a.htab != nullptr, shifted);
-  if (col_tile_width(M, variant) == 8) return col_launch_h<PAD, 8>(hm, conj, a, w_count, s);
-  return col_launch_h<PAD, 16>(hm, conj, a, w_count, s);
+  if (col_tile_width(M, variant) == kTileNarrow) return col_launch_h<PAD, kTileNarrow>(hm, conj, a, w_count, s);
+  return col_launch_h<PAD, kTileWide>(hm, conj, a, w_count, s);
 }
 
 template <int PAD>
@@ -132,15 +142,19 @@ hipError_t col_group_tx(bool conj, bool full, const GroupArgs& g, hipStream_t s)
 template <int PAD, int TX>
 hipError_t col_group_h(int hm, bool conj, bool full, const GroupArgs& g, hipStream_t s) {
   if (hm == kHTable) return col_group_tx<PAD, TX, kHTable>(conj, full, g, s);
-  if (hm == kHMirror) return col_group_tx<PAD, TX, kHMirror>(conj, full, g, s);
+  if constexpr (Geo<M>::WAVE_LOCAL) {
+    if (hm == kHMirror) return col_group_tx<PAD, TX, kHMirror>(conj, full, g, s);
+  } else {
+    if (hm == kHMirror) return hipErrorInvalidValue;
+  }
   return col_group_tx<PAD, TX, kHEval>(conj, full, g, s);
 }
 
 template <int PAD>
 hipError_t col_group_variant(int variant, bool table, bool conj, bool full, const GroupArgs& g, hipStream_t s) {
   const int hm = h_mode(variant, table);
-  if (col_tile_width(M, variant) == 8) return col_group_h<PAD, 8>(hm, conj, full, g, s);
-  return col_group_h<PAD, 16>(hm, conj, full, g, s);
+  if (col_tile_width(M, variant) == kTileNarrow) return col_group_h<PAD, kTileNarrow>(hm, conj, full, g, s);
+  return col_group_h<PAD, kTileWide>(hm, conj, full, g, s);
 }
 
 }  // namespace

@@ -2,6 +2,8 @@
 //
 // A length-M transform is owned by a group of P = M / E lanes; every lane keeps E complex
 // values in registers in the strided layout  lane j0 holds element j0 + P*t, t = 0..E-1.
+// Usually a group lies inside one wavefront (P divides 64); the 1600-point transform
+// (E = 20, P = 80) spans wavefronts and orders its LDS exchanges with block barriers.
 // With this layout every Stockham radix-R stage (R divides E) finds all R inputs of its
 // butterflies in the lane's own registers; only the outputs of a non-final stage are
 // scattered, so they go through the group's LDS region and come back strided.  The final
@@ -178,6 +180,33 @@ struct DFT<3, INV, HALF> {
   }
 };
 
+// 5-point DFT: with t1 = b + e, t2 = c + d, t3 = b - e, t4 = c - d and W = exp(-+2 pi i / 5)
+//   X0 = a + t1 + t2,  X1,4 = a + c1 t1 + c2 t2 -+ i (s1 t3 + s2 t4),
+//   X2,3 = a + c2 t1 + c1 t2 -+ i (s2 t3 - s1 t4)
+// (c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5); the upper sign for the forward transform).
+template <bool INV, bool HALF>
+struct DFT<5, INV, HALF> {
+  static_assert(!HALF, "radix-5 stages are never zero-pruned");
+  static __device__ __forceinline__ void run(float2* v) {
+    constexpr float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    constexpr float s1 = INV ? -0.95105651629515357212f : 0.95105651629515357212f;
+    constexpr float s2 = INV ? -0.58778525229247312917f : 0.58778525229247312917f;
+    const float2 a = v[0];
+    const float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const float2 m1 = cfma(c1, t1, cfma(c2, t2, a));
+    const float2 m2 = cfma(c2, t1, cfma(c1, t2, a));
+    const float2 n1 = cfma(s1, t3, cscale(t4, s2));
+    const float2 n2 = cfma(s2, t3, cscale(t4, -s1));
+    v[0] = cadd(a, cadd(t1, t2));
+    // m -+ i n: (m.x +- n.y, m.y -+ n.x)
+    v[1] = make_float2(m1.x + n1.y, m1.y - n1.x);
+    v[4] = make_float2(m1.x - n1.y, m1.y + n1.x);
+    v[2] = make_float2(m2.x + n2.y, m2.y - n2.x);
+    v[3] = make_float2(m2.x - n2.y, m2.y + n2.x);
+  }
+};
+
 template <bool INV, bool HALF>
 struct DFT<4, INV, HALF> {
   static __device__ __forceinline__ void run(float2* v) {
@@ -310,6 +339,7 @@ template <> struct Plan<256>  { static constexpr int E = 16, NST = 2, SH = 4, RX
 template <> struct Plan<384>  { static constexpr int E = 12, NST = 4, SH = 5, RX = 4, CX = 0;  static constexpr int R[4] = {12, 4, 4, 2}; };
 template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX = 16, CX = 16; static constexpr int R[4] = {8, 8, 8, 0}; };
 template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 5, RX = 0, CX = 4;  static constexpr int R[4] = {16, 16, 4, 0}; };
+template <> struct Plan<1600> { static constexpr int E = 20, NST = 3, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {20, 20, 4, 0}; };
 
 template <int M>
 struct Geo {
@@ -317,8 +347,9 @@ struct Geo {
   static constexpr int P = M / E;  // lanes per transform
   static constexpr int ROW_REGION = M + (M >> Plan<M>::SH) + Plan<M>::RX;
   static constexpr int COL_REGION = M + (M >> Plan<M>::SH) + Plan<M>::CX;
-  static_assert(P <= 64, "one transform must fit in a wavefront");
-  static_assert(64 % P == 0, "transforms must tile a wavefront");
+  // the lanes of one transform lie in one wavefront
+  static constexpr bool WAVE_LOCAL = P <= 64 && 64 % P == 0;
+  static_assert(WAVE_LOCAL || P % 16 == 0, "a group spanning wavefronts is a whole number of 16-lane rows");
 };
 
 // Per-stage twiddle table: stage s (radix R, NS = product of the earlier radices, s >= 1)
@@ -355,6 +386,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS ordering between the lanes of one transform of length M: the wave-level fence when the
+// group lies in one wavefront, a block barrier otherwise (every thread of the block runs every
+// transform, so the barrier is reached uniformly).
+template <int M>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (Geo<M>::WAVE_LOCAL)
+    wave_sync();
+  else
+    __syncthreads();
 }
 
 constexpr bool divides_or_multiple(int a, int b) { return a % b == 0 || b % a == 0; }
@@ -407,7 +449,7 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
     }
   }
   if constexpr (!LAST) {
-    wave_sync();
+    group_sync<M>();
     if constexpr (LIN_R) {
       const int rb = j0 + (j0 >> SH);
 #pragma unroll
@@ -416,7 +458,7 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = lds[lds_slot<M>(j0 + P * t)];
     }
-    wave_sync();
+    group_sync<M>();
   }
 }
 

@@ -42,7 +42,7 @@ __device__ __forceinline__ float2 transmission(float h, const WlConst& c) {
 }
 
 template <int M, int MODE>
-constexpr int row_block_threads() { return row_threads_of_mode(MODE); }
+constexpr int row_block_threads() { return row_threads_for(Geo<M>::P, MODE); }
 
 // ------------------------------------------------------------------------------------------
 // Row pass.  A block owns G = 256 / P consecutive rows (one transform group per row) and
@@ -78,8 +78,9 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
   float hreg[EN];
   if constexpr (MODE == ROW_FWD_FIRST || MODE == ROW_FWD_MID || MODE == ROW_ADJ_MID ||
                 MODE == ROW_ADJ_LAST) {
+    const bool read_h = MODE != ROW_FWD_FIRST || !a.no_layer;
 #pragma unroll
-    for (int t = 0; t < EN; ++t) hreg[t] = a.h[static_cast<size_t>(y) * N + j0 + P * t];
+    for (int t = 0; t < EN; ++t) hreg[t] = read_h ? a.h[static_cast<size_t>(y) * N + j0 + P * t] : 0.f;
   }
 
   if constexpr (MODE == ROW_FWD_FIRST) {
@@ -91,8 +92,13 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       const WlConst c = a.wl[w];
       const int wc = w - a.w_begin;
       float2 reg[E];
+      if (a.no_layer) {
 #pragma unroll
-      for (int t = 0; t < EN; ++t) reg[t] = cmul(uin[t], transmission(hreg[t], c));
+        for (int t = 0; t < EN; ++t) reg[t] = uin[t];
+      } else {
+#pragma unroll
+        for (int t = 0; t < EN; ++t) reg[t] = cmul(uin[t], transmission(hreg[t], c));
+      }
       if (a.store_ckpt && active) {
         float2* ck = a.ckpt + (static_cast<size_t>(a.layer) * a.ckpt_w_stride + wc) * nn +
                      static_cast<size_t>(y) * N;
@@ -223,7 +229,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 }
 
 template <int M, int PAD, int MODE>
-__global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs a) {
+__global__ void __launch_bounds__((row_block_threads<M, MODE>())) row_kernel(RowArgs a) {
   __shared__ float2 lds_all[row_block_threads<M, MODE>() / Geo<M>::P * Geo<M>::ROW_REGION];
   __shared__ float2 tw[twiddle_count<M>()];
   row_body<M, PAD, MODE>(a, blockIdx.x, blockIdx.y, lds_all, tw);
@@ -233,7 +239,7 @@ __global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_kernel(RowArgs 
 // block finds its design's task, patches the per-call buffers into the design's arguments
 // and runs the same body as the single-design kernel.
 template <int M, int PAD, int MODE>
-__global__ void __launch_bounds__(row_threads_of_mode(MODE)) row_group_kernel(GroupArgs g) {
+__global__ void __launch_bounds__((row_block_threads<M, MODE>())) row_group_kernel(GroupArgs g) {
   __shared__ float2 lds_all[row_block_threads<M, MODE>() / Geo<M>::P * Geo<M>::ROW_REGION];
   __shared__ float2 tw[twiddle_count<M>()];
   const int ti = group_task(g, blockIdx.x);
@@ -359,7 +365,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
       const int y = j0 + P * t;
       reg[t] = (y >= in_lo && y < in_hi) ? lds[y] : make_float2(0.f, 0.f);
     }
-    wave_sync();
+    group_sync<M>();
     fft<M, false, HALF>(reg, lds, j0, tw);
 
     // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0:
@@ -432,7 +438,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
       for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], H(j0 + P * t));
     }
     fft<M, true, false>(reg, lds, j0, tw);
-    wave_sync();
+    group_sync<M>();
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
       const int y = j0 + P * t;

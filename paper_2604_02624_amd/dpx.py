@@ -26,7 +26,7 @@ class CDesign(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("layers", ctypes.c_int32), ("n_wl", ctypes.c_int32),
                 ("fov", ctypes.c_int32), ("bin", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("n_medium", ctypes.c_double),
-                ("wl", _dp), ("n_mat", _dp), ("kappa", _dp), ("z", _dp)]
+                ("wl", _dp), ("n_mat", _dp), ("kappa", _dp), ("z", _dp), ("z_in", ctypes.c_double)]
 
 
 class COpts(ctypes.Structure):
@@ -133,6 +133,7 @@ def _c_designs(designs):
         arr[i].n_mat = vec(d["n_mat"])
         arr[i].kappa = vec(d.get("kappa"))
         arr[i].z = vec(d["z"])
+        arr[i].z_in = float(d.get("z_in") or 0.0)
     return arr, keep
 
 

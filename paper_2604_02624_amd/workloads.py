@@ -24,6 +24,7 @@ A design is a plain dict:
     dx, n_medium                    : float  (metres, refractive index)
     wl, n_mat, kappa                : float64 [n_wl]   (kappa may be None)
     z                               : float64 [layers] (z[k] = gap after layer k)
+    z_in (optional)                 : float (input plane -> first layer)
 
 A workload is a dict with ``designs`` (list), ``h`` (list of float32
 [layers, n, n] arrays, metres), ``targets`` (list of float32 [n_wl, T, T]) and
@@ -52,6 +53,19 @@ def cauchy_index(wl_m: np.ndarray, a: float = 1.50, b_um2: float = 0.0045) -> np
     """Cauchy dispersion n = a + b / lambda^2 with lambda in micrometres."""
     wl_um = np.asarray(wl_m, dtype=np.float64) * 1e6
     return a + b_um2 / (wl_um * wl_um)
+
+
+# N-BK7 (Schott) Sellmeier coefficients, lambda in micrometres: n^2 - 1 = sum B_i l^2 / (l^2 - C_i)
+NBK7_B = (1.03961212, 0.231792344, 1.01046945)
+NBK7_C = (0.00600069867, 0.0200179144, 103.560653)
+
+
+def nbk7_index(wl_m: np.ndarray) -> np.ndarray:
+    """Refractive index of N-BK7 glass, the layer material of the paper's designs (Section 4,
+    ref. 54), from the glass maker's Sellmeier formula; no absorption in the visible."""
+    l2 = (np.asarray(wl_m, dtype=np.float64) * 1e6) ** 2
+    n2 = 1.0 + sum(b * l2 / (l2 - c) for b, c in zip(NBK7_B, NBK7_C))
+    return np.sqrt(n2)
 
 
 def make_design(n, layers, wl, n_mat, dx, z, fov, bin_=1, pad=2, n_medium=1.0, kappa=None):
@@ -119,8 +133,36 @@ def _visible_band(cfg: int, n: int, layers: int, n_wl: int, t: int, gray: bool, 
     return d, h, tau
 
 
+def paper_geometry(n_wl: int = 4096, layers: int = 8, n: int = 800, cfg: int = 6):
+    """The Fig. 2 design (Section 2 and Section 4 "Optical forward model"): 800 x 800 N-BK7
+    features per layer at a pitch of half the shortest wavelength (200 nm), K = 8, wavelengths
+    from 750 nm down to 400 nm (longest first), an input aperture and an output field of view
+    of about 69.56 lambda_m (200 samples), 25 x 25 output pixels of 8 x 8 samples, and an axial
+    span of about 1260 lambda_m from the aperture to the output plane, split here into equal
+    gaps (input plane, K layers, output plane: K + 1 gaps).  Smaller n_wl / layers / n keep the
+    same optics for tests."""
+    lam_short, lam_long = 400e-9, 750e-9
+    lam_m = 0.5 * (lam_short + lam_long)
+    dx = 0.5 * lam_short
+    wl = np.linspace(lam_long, lam_short, n_wl, dtype=np.float64)
+    gap = 1260.0 * lam_m / (layers + 1)
+    side = 200 if n >= 400 else n // 4          # aperture / field-of-view side in samples
+    side -= side % 8
+    d = make_design(n=n, layers=layers, wl=wl, n_mat=nbk7_index(wl), dx=dx, z=gap, fov=side,
+                    bin_=8, pad=2)
+    d["z_in"] = gap
+    d["h_max"] = lam_m / (float(nbk7_index(np.array([lam_m]))[0]) - 1.0)
+    a = (n - side) // 2
+    u_in = np.zeros((n, n), np.complex64)
+    u_in[a:a + side, a:a + side] = 1.0
+    h = uniform_heights(rng(cfg, STREAM_HEIGHTS), layers, n, d["h_max"])
+    tau = grayscale_targets(rng(cfg, STREAM_TARGETS), n_wl, side // 8)
+    return d, h, tau, u_in
+
+
 def make_workload(cfg: int) -> dict:
-    """cfg 1..5: the five workloads (small forward, small fwd+adjoint, batched, large, uneven)."""
+    """cfg 1..6: the workloads (small forward, small fwd+adjoint, batched, large, uneven, and
+    the paper's own Fig. 2 geometry)."""
     if cfg in (1, 2):
         d, h, tau = _experiment_pair(cfg)
         designs, hs, taus = [d], [h], [tau]
@@ -142,6 +184,9 @@ def make_workload(cfg: int) -> dict:
             designs.append(d)
             hs.append(h)
             taus.append(tau)
+    elif cfg == 6:
+        d, h, tau, u_in = paper_geometry()
+        return dict(cfg=cfg, designs=[d], h=[h], targets=[tau], u_in=[u_in])
     else:
         raise ValueError(f"unknown workload {cfg}")
     return dict(cfg=cfg, designs=designs, h=hs, targets=taus, u_in=[None] * len(designs))

@@ -39,8 +39,9 @@ double all_forms() {
 }
 
 int main() {
-  const double e[] = {all_forms<2>(), all_forms<3>(), all_forms<4>(), all_forms<6>(),
-                      all_forms<8>(), all_forms<12>(), all_forms<16>()};
+  const double e[] = {all_forms<2>(), all_forms<3>(), all_forms<4>(),  all_forms<5>(),
+                      all_forms<6>(), all_forms<8>(), all_forms<10>(), all_forms<12>(),
+                      all_forms<16>(), all_forms<20>()};
   double worst = 0.0;
   for (double x : e) worst = std::max(worst, x);
   std::printf("%.3e\n", worst);

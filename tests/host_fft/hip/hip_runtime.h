@@ -12,3 +12,4 @@ struct float2 {
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
 #define __builtin_amdgcn_fence(order, scope) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
+inline void __syncthreads() {}
