@@ -44,6 +44,11 @@ Readings of the paper used here (each also listed with the design notes):
   reaches layer 1 after the optional gap z_in (the Fig. 1 schematic, the
   input plane being one of the planes connected by diffraction); z_in = 0
   means u_in is the field at layer 1.
+* Band-limited angular spectrum (an alternative transfer function, off
+  unless a design sets band_limited): H is set to zero where the sampled
+  phase would alias (band_limit below).
+* Phase-only layers (Eq. 3) are the thickness model with a unit index
+  contrast and no dispersion; phase_only_transmission states them directly.
 * Misalignment (Section 2, the "vaccination" against lateral and axial
   displacements): gap l may be lengthened by dz_l and may translate the field
   it delivers by (sx_l, sy_l), a factor exp(-j 2 pi (fx sx + fy sy)) on H.
@@ -121,8 +126,16 @@ def spatial_frequencies(M: int, dx: float) -> np.ndarray:
     return signed_index(M).astype(np.float64) / (M * dx)
 
 
+def band_limit(M: int, dx: float, wl: float, n_medium: float, z: float) -> float:
+    """Band limit of the sampled transfer function (Matsushima and Shimobaba's band-limited
+    angular spectrum): the phase 2 pi z sqrt(k^2 - f^2), k = n_m / lambda, sampled every
+    1 / (M dx) in f, changes by at most pi between samples while its local frequency
+    z |f| / sqrt(k^2 - f^2) stays within M dx / 2, i.e. for |f| <= k / sqrt((2 z / (M dx))^2 + 1)."""
+    return (n_medium / wl) / np.sqrt((2.0 * z / (M * dx)) ** 2 + 1.0)
+
+
 def transfer_function(M: int, dx: float, wl: float, n_medium: float, z: float,
-                      shift=(0.0, 0.0)) -> np.ndarray:
+                      shift=(0.0, 0.0), band_limited: bool = False) -> np.ndarray:
     """H[ky, kx] = exp(+j 2 pi z sqrt(q)) for q = (n_m/lambda)^2 - fx^2 - fy^2 > 0, else 0.
 
     With shift = (sx, sy) in metres H is multiplied by exp(-j 2 pi (fx sx + fy sy)): the
@@ -133,6 +146,9 @@ def transfer_function(M: int, dx: float, wl: float, n_medium: float, z: float,
     prop = q > 0.0
     root = np.sqrt(np.where(prop, q, 0.0))
     H = np.where(prop, np.exp(1j * TWO_PI * z * root), 0.0)
+    if band_limited:
+        lim = band_limit(M, dx, wl, n_medium, z)
+        H = np.where((np.abs(f[None, :]) <= lim) & (np.abs(f[:, None]) <= lim), H, 0.0)
     sx, sy = float(shift[0]), float(shift[1])
     if sx != 0.0 or sy != 0.0:
         H = H * np.exp(-1j * TWO_PI * (f[None, :] * sx + f[:, None] * sy))
@@ -154,12 +170,13 @@ def crop_centered(U: np.ndarray, N: int) -> np.ndarray:
 
 
 def propagate(u: np.ndarray, pad: int, dx: float, wl: float, n_medium: float, z: float,
-              mode: str = "naive", adjoint: bool = False, shift=(0.0, 0.0)) -> np.ndarray:
+              mode: str = "naive", adjoint: bool = False, shift=(0.0, 0.0),
+              band_limited: bool = False) -> np.ndarray:
     """One gap: pad -> DFT2 -> x H -> IDFT2 -> crop.  ``adjoint`` applies the Hermitian
     adjoint of that linear map, which is the same chain with conj(H)."""
     N = u.shape[-1]
     M = pad * N
-    H = transfer_function(M, dx, wl, n_medium, z, shift)
+    H = transfer_function(M, dx, wl, n_medium, z, shift, band_limited)
     if adjoint:
         H = np.conj(H)
     V = idft2(H * dft2(pad_centered(u, M), mode), mode)
@@ -216,6 +233,27 @@ def gap_jitter_from_layer_offsets(Dz: np.ndarray) -> np.ndarray:
     return np.append(Dz[1:], 0.0) - Dz
 
 
+def quantize_heights(h: np.ndarray, h_max: float, bits: int) -> np.ndarray:
+    """Phase bit depth B (Section 2, fabrication limits): 2^B thickness levels k h_max / (2^B - 1),
+    k = 0 .. 2^B - 1, each height taken to the nearest level (ties to even), heights outside
+    [0, h_max] to the end levels.  The level index is an integer decided by floating point, so it
+    is decided in single precision: k = rint(h * s) with s = fl32((2^B - 1) / h_max), the level
+    value fl32(k) * fl32(h_max / (2^B - 1))."""
+    levels = (1 << bits) - 1
+    s = np.float32(levels / h_max)
+    step = np.float32(h_max / levels)
+    k = np.rint(np.asarray(h, np.float32) * s)
+    k = np.clip(k, np.float32(0), np.float32(levels))
+    return (k * step).astype(np.float32)
+
+
+def phase_only_transmission(phi: np.ndarray, wl: float, lam_ref: float) -> np.ndarray:
+    """Eq. 3, a phase-only pixel (the spatial light modulator of the experiment), with the sign
+    reading of Eq. 1 (+j): exp(+j phi lambda_ref / lambda), phi being the phase at lambda_ref of a
+    fixed optical path."""
+    return np.exp(1j * np.asarray(phi, np.float64) * (lam_ref / wl))
+
+
 def _kappa(design, w):
     k = design.get("kappa")
     return 0.0 if k is None else float(k[w])
@@ -249,18 +287,21 @@ def forward(design: dict, h: np.ndarray, u_in=None, mode: str = "naive", keep: b
     vs = np.zeros((len(ws), K, N, N), np.complex128) if keep else None
     os_ = np.zeros((len(ws), design["fov"], design["fov"]), np.complex128) if keep else None
     z_in = float(design.get("z_in") or 0.0)
+    bl = bool(design.get("band_limited"))
     for i, w in enumerate(ws):
         wl, nm = float(design["wl"][w]), float(design["n_mat"][w])
         u = u0
         if z_in > 0.0:
             # the input plane (u_in, e.g. the illumination aperture) lies z_in before layer 1
-            u = propagate(u0, design["pad"], design["dx"], wl, design["n_medium"], z_in, mode)
+            u = propagate(u0, design["pad"], design["dx"], wl, design["n_medium"], z_in, mode,
+                          band_limited=bl)
         for l in range(K):
             v = transmission(h64[l], wl, nm, _kappa(design, w), design["n_medium"]) * u
             if keep:
                 vs[i, l] = v
             z, sh = gap(design, l)
-            u = propagate(v, design["pad"], design["dx"], wl, design["n_medium"], z, mode, shift=sh)
+            u = propagate(v, design["pad"], design["dx"], wl, design["n_medium"], z, mode, shift=sh,
+                          band_limited=bl)
         o = u[fs, fs]
         if keep:
             os_[i] = o
@@ -315,7 +356,7 @@ def grad(design: dict, h: np.ndarray, u_in, dl_di: np.ndarray, mode: str = "naiv
         for l in range(K - 1, -1, -1):
             z, sh = gap(design, l)
             g = propagate(g, design["pad"], design["dx"], wl, design["n_medium"], z, mode,
-                          adjoint=True, shift=sh)
+                          adjoint=True, shift=sh, band_limited=bool(design.get("band_limited")))
             p = np.conj(g) * vs[i, l]
             dh[l] += -c_t * p.imag - c_a * p.real
             g = np.conj(transmission(h64[l], wl, nm, _kappa(design, w), design["n_medium"])) * g

@@ -7,24 +7,25 @@ import tests.test_oracle_pins as pins
 import tests.test_oracle_training as tpins
 import tests.test_oracle_misalignment as mpins
 import tests.test_oracle_input_gap as gpins
+import tests.test_oracle_f4 as fpins
 from oracle import dpx_oracle as o
 
 TWO_PI = 2 * np.pi
 
 
-def _h_sign_flipped(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
+def _h_sign_flipped(M, dx, wl, n_medium, z, shift=(0.0, 0.0), band_limited=False):
     f = o.spatial_frequencies(M, dx)
     q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
     return np.where(q > 0, np.exp(-1j * TWO_PI * z * np.sqrt(np.maximum(q, 0))), 0)
 
 
-def _h_no_cut(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
+def _h_no_cut(M, dx, wl, n_medium, z, shift=(0.0, 0.0), band_limited=False):
     f = o.spatial_frequencies(M, dx)
     q = (n_medium / wl) ** 2 - f[None, :] ** 2 - f[:, None] ** 2
     return np.exp(1j * TWO_PI * z * np.sqrt(q.astype(complex)))
 
 
-def _h_axes_scaled(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
+def _h_axes_scaled(M, dx, wl, n_medium, z, shift=(0.0, 0.0), band_limited=False):
     f = o.spatial_frequencies(M, dx)
     q = (n_medium / wl) ** 2 - f[None, :] ** 2 - 0.5 * f[:, None] ** 2
     return np.where(q > 0, np.exp(1j * TWO_PI * z * np.sqrt(np.maximum(q, 0))), 0)
@@ -35,7 +36,7 @@ _orig_transfer = o.transfer_function
 
 def _ramp_mutant(ramp):
     """A transfer function whose shift ramp is computed by ``ramp(f, sx, sy)``."""
-    def H(M, dx, wl, n_medium, z, shift=(0.0, 0.0)):
+    def H(M, dx, wl, n_medium, z, shift=(0.0, 0.0), band_limited=False):
         f = o.spatial_frequencies(M, dx)
         return _orig_transfer(M, dx, wl, n_medium, z) * ramp(f, M, dx, float(shift[0]), float(shift[1]))
     return H
@@ -72,6 +73,34 @@ _orig_forward = o.forward
 
 def _forward_without_input_gap(design, *args, **kw):
     return _orig_forward(dict(design, z_in=0.0), *args, **kw)
+
+
+def _quantize_ties_up(h, h_max, bits):
+    levels = (1 << bits) - 1
+    k = np.floor(np.asarray(h, np.float32) * np.float32(levels / h_max) + np.float32(0.5))
+    return (np.clip(k, 0, levels) * np.float32(h_max / levels)).astype(np.float32)
+
+
+def _quantize_power_of_two_levels(h, h_max, bits):
+    levels = 1 << bits
+    k = np.rint(np.asarray(h, np.float32) * np.float32(levels / h_max))
+    return (np.clip(k, 0, levels) * np.float32(h_max / levels)).astype(np.float32)
+
+
+def _band_limit_without_factor_two(M, dx, wl, n_medium, z):
+    return (n_medium / wl) / np.sqrt((z / (M * dx)) ** 2 + 1.0)
+
+
+def _h_band_limited_x_only(M, dx, wl, n_medium, z, shift=(0.0, 0.0), band_limited=False):
+    H = _orig_transfer(M, dx, wl, n_medium, z, shift)
+    if band_limited:
+        f = o.spatial_frequencies(M, dx)
+        H = np.where((np.abs(f[None, :]) <= o.band_limit(M, dx, wl, n_medium, z)), H, 0.0)
+    return H
+
+
+def _phase_only_sign_flipped(phi, wl, lam_ref):
+    return np.exp(-1j * np.asarray(phi, float) * (lam_ref / wl))
 
 
 def _idft_no_norm(V, mode="naive"):
@@ -140,6 +169,11 @@ def _swap_shortest_first(ps, wl):
     return src
 
 CASES = [
+    ("quantize_heights", _quantize_ties_up, [fpins.test_quantiser_ties_go_to_even_levels]),
+    ("quantize_heights", _quantize_power_of_two_levels, [fpins.test_quantiser_one_bit_and_exact_levels]),
+    ("band_limit", _band_limit_without_factor_two, [fpins.test_band_limit_is_where_the_sampled_phase_steps_by_pi, (64, 20e-6)]),
+    ("transfer_function", _h_band_limited_x_only, [fpins.test_band_limited_transfer_function_is_a_symmetric_mask]),
+    ("phase_only_transmission", _phase_only_sign_flipped, [fpins.test_phase_only_layer_is_the_unit_contrast_thickness_model]),
     ("forward", _forward_without_input_gap, [gpins.test_input_gap_equals_a_leading_transparent_layer]),
     ("transfer_function", _h_ramp_sign_flipped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
     ("transfer_function", _h_ramp_axes_swapped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
