@@ -93,6 +93,12 @@ typedef struct dpx_design {
                            layer 1, metres; 0 = u_in is the field at layer 1 (Fig. 1: the input
                            plane, the layers and the output plane are connected by diffraction).
                            A design with z_in > 0 runs the per-design schedule. */
+  int32_t band_limited; /* 0: angular spectrum as above; 1: band-limited angular spectrum
+                           (Matsushima and Shimobaba): H = 0 where |fx| or |fy| exceeds
+                           (n_m / lambda) / sqrt((2 z / (M dx))^2 + 1), the frequency beyond which
+                           the sampled transfer function aliases.  Uses the per-element column
+                           variants (0, 1) and the per-design schedule; not with transfer tables,
+                           the matrix-core variant or lateral translations. */
 } dpx_design;
 
 typedef struct dpx_opts {
@@ -227,6 +233,16 @@ dpx_status dpx_plan_set_wavelengths(dpx_plan* plan, int32_t design, const double
  * with the matrix-core column variant.  On error the plan is unchanged. */
 dpx_status dpx_plan_set_misalignment(dpx_plan* plan, int32_t design, const double* dz,
                                      const double* shift_x, const double* shift_y, int32_t n_gaps);
+
+/* Phase bit depth (paper Section 2, limited axial resolution of fabricated thicknesses):
+ * h_q[i] = k * (h_max / (2^bits - 1)) with k = rint(h[i] * (2^bits - 1) / h_max) (ties to even)
+ * clamped to [0, 2^bits - 1]; the level index is decided in single precision with the scale and
+ * the step rounded once from double.
+ *   h, h_q  [n] f32 (device; h_q may equal h)    h_max > 0 metres    1 <= bits <= 24
+ * Training with quantised heights runs the forward and backward on h_q and applies dL/dh_q to
+ * the continuous heights (straight-through).  Errors: DPX_E_ARG for bad arguments. */
+dpx_status dpx_quantize_heights(const float* h, float* h_q, int64_t n, double h_max, int32_t bits,
+                                void* stream);
 
 /* Totals over all designs: h floats, u_in complex elements, image floats. */
 dpx_status dpx_plan_sizes(const dpx_plan* plan, int64_t* h_count, int64_t* u_count,

@@ -54,6 +54,7 @@ struct Design {
   std::vector<double> wl, n_mat, kappa, z;
   std::vector<double> dz, sx, sy;  // per gap: axial jitter, lateral translation (metres)
   double z_in = 0.0;               // input plane -> layer 1 (0: u_in is the field at layer 1)
+  bool band = false;               // band-limited angular spectrum
   int64_t h_off, u_off, img_off;
   // launch geometry
   int wl_chunk;      // wavelengths per chunk (spec buffer depth per lane)
@@ -207,6 +208,11 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
         return fail(DPX_E_ARG, "design %d: z[%d] must be finite and >= 0", i, l);
     if (!(std::isfinite(d.z_in) && d.z_in >= 0.0))
       return fail(DPX_E_ARG, "design %d: z_in must be finite and >= 0", i);
+    if (d.band_limited != 0 && d.band_limited != 1) return fail(DPX_E_ARG, "design %d: band_limited must be 0 or 1", i);
+    if (d.band_limited && o && (o->force_variant > 1 || o->transfer_table == 2))
+      return fail(DPX_E_UNSUPPORTED,
+                  "design %d: the band-limited spectrum runs the per-element column variants (0, 1), "
+                  "without transfer tables", i);
     const int M = d.pad * d.n;
     if (o && o->force_variant >= 0 && dpx::fft_size_supported(M) &&
         !dpx::col_variant_supported(M, d.pad, o->force_variant))
@@ -234,6 +240,7 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   d.dx = src.dx;
   d.n_m = src.n_medium;
   d.z_in = src.z_in;
+  d.band = src.band_limited != 0;
   const int P = dpx::row_lanes_per_transform(d.M);
   (void)P;
   d.row_group = dpx::row_rows_per_block(d.M, dpx::ROW_FWD_MID);
@@ -261,7 +268,7 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   // LDS-resident path for short transforms (opts.small_path = 1): every wavelength is one
   // block with one dL/dh slot, the whole design one chunk
   d.lds = o.small_path == 1 && o.checkpoint_mode == 0 && o.streams <= 1 && o.force_variant < 0 &&
-          src.z_in == 0.0 &&
+          src.z_in == 0.0 && src.band_limited == 0 &&
           o.transfer_table != 2 && dpx::lds_path_supported(d.M, d.pad);
   if (d.lds) {
     chunk = d.W;
@@ -274,6 +281,9 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   d.slots_per_lane = (chunk + wpb - 1) / wpb;
   d.nslots = d.lanes * d.slots_per_lane;
   d.col_variant = o.force_variant >= 0 ? o.force_variant : dpx::default_col_variant(d.M);
+  // the band-limited spectrum is applied by the per-element evaluation: the mirrored variants'
+  // tile widths without the mirror
+  if (src.band_limited && d.col_variant >= 2 && d.col_variant <= 3) d.col_variant -= 2;
   // transfer tables (opts.transfer_table: 2 = always; 0 automatic and 1 = never: measured on
   // MI355X, reading H costs the column pass more load traffic and latency than evaluating it
   // saves arithmetic)
@@ -470,6 +480,7 @@ ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0
   c.zrev = (layer < 0 ? d.z_in : d.z[layer] + d.dz[layer]) / md;
   c.sx = layer < 0 ? 0.0 : d.sx[layer] / md;
   c.sy = layer < 0 ? 0.0 : d.sy[layer] / md;
+  c.band_limited = d.band ? 1 : 0;
   c.n = d.N;
   c.in_lo = in_lo;
   c.in_hi = in_hi;
@@ -735,7 +746,7 @@ void add_simple_group(std::vector<GroupLaunch>& out, GroupKind kind, const std::
 bool groupable(const dpx_plan* p) {
   if (p->opts.checkpoint_mode != 0) return false;
   for (const auto& d : p->designs)
-    if (d.nchunks != 1 || d.lanes != 1 || d.col_variant > 3 || d.z_in > 0.0) return false;
+    if (d.nchunks != 1 || d.lanes != 1 || d.col_variant > 3 || d.z_in > 0.0 || d.band) return false;
   return true;
 }
 
@@ -944,7 +955,7 @@ dpx_status join_lanes(dpx_plan* p, const Design& d, hipStream_t s) {
 // of layer 0 on a zeroed spectrum buffer) and keeps the fastest.  All variants produce the
 // same bits, so the choice changes speed only.
 dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
-  const int key = d.M * 4 + d.pad;
+  const int key = (d.M * 4 + d.pad) * 2 + (d.band ? 1 : 0);
   auto it = cache.find(key);
   if (it != cache.end()) {
     d.col_variant = it->second;
@@ -956,12 +967,13 @@ dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
   DPX_HIP(hipEventCreate(&e0));
   DPX_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_v = dpx::default_col_variant(d.M);
+  int best_v = d.band ? d.col_variant : dpx::default_col_variant(d.M);
   const bool was_timing = p->timing;
   p->timing = false;
   for (int v = 0; v < dpx::kColVariants; ++v) {
     if (!dpx::col_variant_supported(d.M, d.pad, v)) continue;
     if (v == 4 && !p->dft.count(d.M * 4 + d.pad)) continue;
+    if (d.band && v > 1) continue;
     d.col_variant = v;
     DPX_TRY(run_col(p, d, 0, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
     DPX_HIP(hipEventRecord(e0, nullptr));
@@ -1123,7 +1135,8 @@ dpx_status dpx_plan_query(const dpx_design* ds, int32_t nd, const dpx_opts* opts
     layout_design(ds[i], o, d);
     tot += d.bytes;
     ms[d.M] = 1;
-    groupable_all = groupable_all && d.nchunks == 1 && d.lanes == 1 && d.col_variant <= 3 && d.z_in == 0.0;
+    groupable_all = groupable_all && d.nchunks == 1 && d.lanes == 1 && d.col_variant <= 3 && d.z_in == 0.0 &&
+                    !d.band;
   }
   if (o.schedule == 2 && !groupable_all)
     return fail(DPX_E_UNSUPPORTED,
@@ -1425,6 +1438,8 @@ dpx_status dpx_plan_set_misalignment(dpx_plan* p, int32_t i, const double* dz, c
                 "evaluated in the column pass (no grouped schedule, LDS-resident path or tables)", i);
   if (lateral && d.col_variant == 4)
     return fail(DPX_E_UNSUPPORTED, "design %d: the matrix-core column variant has no lateral translation", i);
+  if (lateral && d.band)
+    return fail(DPX_E_UNSUPPORTED, "design %d: no lateral translation with the band-limited spectrum", i);
   if (lateral && !dpx::col_translation_supported(d.M))
     return fail(DPX_E_UNSUPPORTED, "design %d: no lateral translation at transform length %d", i, d.M);
   // captured graphs hold the old kernel arguments
@@ -1615,6 +1630,21 @@ dpx_status dpx_adam_step(float* theta, float* h, const float* dl_dh, float* m, f
   a.c2 = static_cast<float>(1.0 / (1.0 - std::pow(b2, step)));
   hipError_t e = dpx::launch_adam_sigmoid(theta, h, dl_dh, m, v, n, a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(DPX_E_DEVICE, "Adam step launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+dpx_status dpx_quantize_heights(const float* h, float* h_q, int64_t n, double h_max, int32_t bits, void* stream) {
+  if (n < 0) return fail(DPX_E_ARG, "n must be >= 0");
+  if (bits < 1 || bits > 24) return fail(DPX_E_ARG, "bits must be in [1, 24] (got %d)", bits);
+  if (!(std::isfinite(h_max) && h_max > 0.0)) return fail(DPX_E_ARG, "h_max must be finite and > 0");
+  if (n == 0) return ok();
+  DPX_TRY(check_ptr(h, 4, "h"));
+  DPX_TRY(check_ptr(h_q, 4, "h_q"));
+  DPX_TRY(sticky_check());
+  const double levels = static_cast<double>((1 << bits) - 1);
+  hipError_t e = dpx::launch_quantize(h, h_q, n, static_cast<float>(levels / h_max), static_cast<float>(h_max / levels),
+                                      static_cast<float>(levels), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "quantiser launch failed: %s", hipGetErrorString(e));
   return ok();
 }
 

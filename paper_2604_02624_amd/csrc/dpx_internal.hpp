@@ -68,6 +68,7 @@ struct ColArgs {
                              // frequency index (0, 0 unless the plan has a misalignment)
   float2 ystep;              // exp(-i 2 pi P sy), P = rows between a lane's registers (set by
                              // the launcher of a translated gap)
+  int band_limited;          // band-limited angular spectrum (per-element H evaluation only)
   int n;
   int in_lo, in_hi;          // rows holding non-zero input (others read as zero)
   int out_lo, out_hi;        // rows whose output is kept
@@ -250,6 +251,8 @@ struct AdamArgs {
   float omb1, omb2;  // 1 - b1, 1 - b2 (formed in double)
   float c1, c2;      // 1 / (1 - b1^t), 1 / (1 - b2^t)
 };
+hipError_t launch_quantize(const float* h, float* out, int64_t n, float scale, float step, float kmax,
+                           hipStream_t s);
 hipError_t launch_adam_sigmoid(float* theta, float* h, const float* dl_dh, float* m, float* v, int64_t n,
                                const AdamArgs& a, hipStream_t s);
 // per-wavelength PSNR of one design's [W][T][T] images -> out [W]

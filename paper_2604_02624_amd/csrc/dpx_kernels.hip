@@ -149,6 +149,15 @@ __global__ void dh_group_kernel(GroupArgs g, float* __restrict__ dl_dh) {
 //   theta -= lr (m c1) / (sqrt(v c2) + eps)  with c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t),
 // then h = h_max sigmoid(theta).  Arithmetic in single precision; 1 - b1, 1 - b2 and the bias
 // corrections come from the host, formed in double.
+// Phase bit depth: the nearest of the levels k step, k = 0 .. kmax (ties to even), the level
+// index decided in single precision as rint(h scale), clamped to the end levels.
+__global__ void quantize_kernel(const float* h, float* out, int64_t n, float scale, float step, float kmax) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float k = fminf(fmaxf(rintf(h[i] * scale), 0.0f), kmax);
+  out[i] = k * step;
+}
+
 __global__ void adam_sigmoid_kernel(float* __restrict__ theta, float* __restrict__ h, const float* __restrict__ dl_dh,
                                     float* __restrict__ m, float* __restrict__ v, int64_t n, AdamArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -458,6 +467,14 @@ hipError_t launch_loss_sum_group(const LossTask* tasks, int ntasks, double* loss
 hipError_t launch_dh_group(const GroupArgs& g, float* dl_dh, hipStream_t s) {
   if (g.ntasks < 1 || g.ntasks > kMaxGroupTasks) return hipErrorInvalidValue;
   dh_group_kernel<<<group_grid(g), kGroupThreads, 0, s>>>(g, dl_dh);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float* h, float* out, int64_t n, float scale, float step, float kmax,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int th = 256;
+  quantize_kernel<<<static_cast<unsigned>((n + th - 1) / th), th, 0, s>>>(h, out, n, scale, step, kmax);
   return hipGetLastError();
 }
 

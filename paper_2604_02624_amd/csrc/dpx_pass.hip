@@ -58,8 +58,8 @@ hipError_t row_group_mode(int mode, const GroupArgs& g, hipStream_t s) {
 
 // H source of a launch: the table when the arguments carry one, the per-element evaluation
 // with the translation ramp for a translated gap, else the variant's evaluation
-int h_mode(int variant, bool table, bool shifted = false) {
-  return table ? kHTable : shifted ? kHShift : (variant >= 2 ? kHMirror : kHEval);
+int h_mode(int variant, bool table, bool shifted = false, bool band = false) {
+  return table ? kHTable : band ? kHBand : shifted ? kHShift : (variant >= 2 ? kHMirror : kHEval);
 }
 
 // every aperture row in and out (the row-range tests compile away)
@@ -87,6 +87,7 @@ constexpr int kTileWide = Geo<M>::WAVE_LOCAL ? 16 : 8;
 template <int PAD, int TX>
 hipError_t col_launch_h(int hm, bool conj, const ColArgs& a, int w_count, hipStream_t s) {
   if (hm == kHTable) return col_launch<PAD, TX, kHTable>(conj, a, w_count, s);
+  if (hm == kHBand) return col_launch<PAD, TX, kHBand>(conj, a, w_count, s);
   if constexpr (Geo<M>::WAVE_LOCAL) {
     if (hm == kHMirror) return col_launch<PAD, TX, kHMirror>(conj, a, w_count, s);
     if (hm == kHShift) return col_launch<PAD, TX, kHShift>(conj, a, w_count, s);
@@ -106,7 +107,7 @@ hipError_t col_variant(int variant, bool conj, const ColArgs& args, int w_count,
     const double ph = -2.0 * 3.14159265358979323846 * (static_cast<double>(Geo<M>::P) * a.sy);
     a.ystep = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
   }
-  const int hm = h_mode(variant, a.htab != nullptr, shifted);
+  const int hm = h_mode(variant, a.htab != nullptr, shifted, a.band_limited != 0);
   if (col_tile_width(M, variant) == kTileNarrow) return col_launch_h<PAD, kTileNarrow>(hm, conj, a, w_count, s);
   return col_launch_h<PAD, kTileWide>(hm, conj, a, w_count, s);
 }

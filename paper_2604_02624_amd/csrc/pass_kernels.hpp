@@ -271,8 +271,9 @@ __device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
 // Where a column pass takes the transfer function from: evaluated for every element, evaluated
 // for the rows ky <= M/2 and shared with the mirrored rows across lanes, or read from the
 // plan's table; a translated gap shares the symmetric part like the mirror form and multiplies
-// every element by its own translation ramp.
-constexpr int kHEval = 0, kHMirror = 1, kHTable = 2, kHShift = 3;
+// every element by its own translation ramp; the band-limited spectrum evaluates every element
+// inside the band.
+constexpr int kHEval = 0, kHMirror = 1, kHTable = 2, kHShift = 3, kHBand = 4;
 
 // Block (bx, by) of a column pass: column tile bx of gx, wavelength block by.  The blocks of
 // one pass are numbered bx + gx by from a multiple of 16 in launch order.
@@ -309,7 +310,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
   // hidden; without it those registers would not fit next to the full-length transform and
   // the rows go straight to LDS.  Row k of a lane is one buffer load at the lane's 32-bit
   // byte offset plus the scalar offset k P M 8, so no per-row address stays live.
-  constexpr bool PREFETCH = HALF && HM != kHShift;
+  constexpr bool PREFETCH = HALF && HM != kHShift && HM != kHBand;
   const int wb = by * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
   const unsigned voff = static_cast<unsigned>((((FULL ? 0 : a.in_lo) + yy) * M + kx0 + cc) * 8);
@@ -372,7 +373,22 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
     // read from the plan's table of H(|kx|, |ky|) when there is one, else evaluated here.
     const double base = c.q0 - static_cast<double>(kxs * kxs);
     auto H = [&](int ky) { return transfer<M, CONJ>(a.zrev, base, ky); };
-    if constexpr (HM == kHTable) {
+    if constexpr (HM == kHEval) {
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], H(j0 + P * t));
+    } else if constexpr (HM == kHBand) {
+      // band-limited angular spectrum: H = 0 where |kx| or |ky| exceeds the band limit
+      // sqrt(q0 / (4 zrev^2 + 1)) (in frequency indices), beyond which the sampled phase aliases
+      const double lim = c.q0 / (4.0 * a.zrev * a.zrev + 1.0);
+      const bool col_in = static_cast<double>(kxs * kxs) <= lim;
+#pragma unroll
+      for (int t = 0; t < E; ++t) {
+        const int ky = j0 + P * t;
+        const int kys = ky < M / 2 ? ky : ky - M;
+        const bool in = col_in && static_cast<double>(kys * kys) <= lim;
+        reg[t] = in ? cmul(reg[t], H(ky)) : make_float2(0.f, 0.f);
+      }
+    } else if constexpr (HM == kHTable) {
       // table row of |kx|: every lane reads its E values (rows ky and M - ky share an entry)
       constexpr int HS = M / 2 + 1;
       const float2* hrow = a.htab + (static_cast<size_t>(a.w_begin + w) * HS + (kxs < 0 ? -kxs : kxs)) * HS;
@@ -433,9 +449,6 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
         }
         cur = nxt;
       }
-    } else {
-#pragma unroll
-      for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], H(j0 + P * t));
     }
     fft<M, true, false>(reg, lds, j0, tw);
     group_sync<M>();

@@ -26,7 +26,8 @@ class CDesign(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("layers", ctypes.c_int32), ("n_wl", ctypes.c_int32),
                 ("fov", ctypes.c_int32), ("bin", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("n_medium", ctypes.c_double),
-                ("wl", _dp), ("n_mat", _dp), ("kappa", _dp), ("z", _dp), ("z_in", ctypes.c_double)]
+                ("wl", _dp), ("n_mat", _dp), ("kappa", _dp), ("z", _dp), ("z_in", ctypes.c_double),
+                ("band_limited", ctypes.c_int32)]
 
 
 class COpts(ctypes.Structure):
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.dpx_plan_set_wavelengths.restype = ctypes.c_int
     lib.dpx_plan_set_misalignment.argtypes = [vp, i32, vp, vp, vp, i32]
     lib.dpx_plan_set_misalignment.restype = ctypes.c_int
+    lib.dpx_quantize_heights.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, i32, vp]
+    lib.dpx_quantize_heights.restype = ctypes.c_int
     lib.dpx_timing_enable.argtypes = [vp, i32]
     lib.dpx_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -134,6 +137,7 @@ def _c_designs(designs):
         arr[i].kappa = vec(d.get("kappa"))
         arr[i].z = vec(d["z"])
         arr[i].z_in = float(d.get("z_in") or 0.0)
+        arr[i].band_limited = 1 if d.get("band_limited") else 0
     return arr, keep
 
 
@@ -415,3 +419,17 @@ def adam_step(theta, h, dl_dh, m, v, step, h_max, lr=1e-3, b1=0.9, b2=0.999, eps
             raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} elements")
     _check(lib, lib.dpx_adam_step(_ptr(theta), _ptr(h), _ptr(dl_dh), _ptr(m), _ptr(v), n, int(step),
                                   float(lr), float(b1), float(b2), float(eps), float(h_max), _stream(stream)))
+
+
+def quantize_heights(h, h_max, bits, out=None, stream=None):
+    """Heights on 2^bits levels over [0, h_max] (dpx_quantize_heights); out may be h."""
+    import torch
+    lib = load_library()
+    if not (h.is_cuda and h.dtype == torch.float32 and h.is_contiguous()):
+        raise ValueError("h must be a contiguous float32 device tensor")
+    if out is None:
+        out = torch.empty_like(h)
+    if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() == h.numel()):
+        raise ValueError("out must be a contiguous float32 device tensor like h")
+    _check(lib, lib.dpx_quantize_heights(_ptr(h), _ptr(out), h.numel(), float(h_max), int(bits), _stream(stream)))
+    return out

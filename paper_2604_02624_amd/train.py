@@ -13,7 +13,9 @@ dpx_forward, dpx_loss, dpx_backward on the batch's plan and dpx_adam_step on the
 One plan (one workspace) serves every batch of a size: it is rebound to the batch's wavelengths
 with dpx_plan_set_wavelengths when the batch changes.  With `misalign = (d_xy, d_z)` every step
 draws a new misalignment of the layers (uniform in +-d_xy laterally, +-d_z axially) and trains
-through it ("vaccination", Section 2).
+through it ("vaccination", Section 2).  With `bits` the forward and backward run on heights
+quantised to that phase bit depth and dL/dh_q updates the continuous heights (straight-through;
+Section 2, training with the bit depth of the fabrication).
 """
 from __future__ import annotations
 
@@ -42,7 +44,7 @@ class Trainer:
     def __init__(self, design: dict, targets: np.ndarray, h_max: float, theta0: np.ndarray | None = None,
                  batch: int = 128, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8,
                  u_in: np.ndarray | None = None, plan_opts: dict | None = None,
-                 misalign: tuple | None = None, misalign_seed: int = 0):
+                 misalign: tuple | None = None, misalign_seed: int = 0, bits: int | None = None):
         import torch
         self.torch = torch
         self.design = design
@@ -68,6 +70,7 @@ class Trainer:
             self.u = torch.view_as_real(torch.as_tensor(np.asarray(u_in, np.complex64))).reshape(-1).cuda()
         self.step_count = 0
         self.misalign = misalign
+        self.bits = bits
         self._mis_rng = np.random.default_rng(misalign_seed)
         self.last_offsets = None
         self.set_targets(targets)
@@ -75,6 +78,7 @@ class Trainer:
         self._I = {n: torch.empty(n * T * T, device="cuda") for n in self._plans}
         self._g = {n: torch.empty(n * T * T, device="cuda") for n in self._plans}
         self._dh = torch.empty_like(self.theta)
+        self._hq = torch.empty_like(self.theta)
 
     def set_targets(self, targets: np.ndarray):
         self.targets = np.ascontiguousarray(targets, np.float32)
@@ -101,9 +105,10 @@ class Trainer:
                                                            *self.misalign)
             self.last_offsets = (lateral, axial)
             p.set_misalignment(0, *robustness.gap_offsets(lateral, axial))
-        p.forward(self.h, self.u, self._I[n])
+        hh = self.heights_used(self.bits)
+        p.forward(hh, self.u, self._I[n])
         L, g = p.loss(self._I[n], self.tau[group], dl_di=self._g[n])
-        p.backward(self.h, self.u, g, self._dh)
+        p.backward(hh, self.u, g, self._dh)
         self.step_count += 1
         dpx.adam_step(self.theta, self.h, self._dh, self.m, self.v, self.step_count, self.h_max,
                       lr=self.lr, b1=self.b1, b2=self.b2, eps=self.eps)
@@ -114,16 +119,24 @@ class Trainer:
         losses = [self.train_step(int(gi)) for gi in rng.permutation(len(self.groups))]
         return float(self.torch.cat(losses).mean().cpu())
 
-    def evaluate(self, offsets=None) -> np.ndarray:
+    def heights_used(self, bits=None):
+        """The device heights a pass runs on: h, or h quantised to `bits` (in a buffer)."""
+        if bits is None:
+            return self.h
+        return dpx.quantize_heights(self.h, self.h_max, bits, out=self._hq)
+
+    def evaluate(self, offsets=None, bits=None) -> np.ndarray:
         """Per-wavelength PSNR (dB) of the current heights, in wavelength order, aligned or with
-        the layer displacements offsets = (lateral [K, 2], axial [K])."""
+        the layer displacements offsets = (lateral [K, 2], axial [K]), and quantised to `bits`
+        (test bit depth) when given."""
         gaps = (None, None, None) if offsets is None else robustness.gap_offsets(*offsets)
         for p in self._plans.values():
             p.set_misalignment(0, *gaps)
+        hh = self.heights_used(bits)
         out = []
         for gi, g in enumerate(self.groups):
             p = self.plan(gi)
-            I = p.forward(self.h, self.u, self._I[len(g)])
+            I = p.forward(hh, self.u, self._I[len(g)])
             out.append(p.psnr(I, self.tau[gi]))
         if offsets is not None:
             for p in self._plans.values():
