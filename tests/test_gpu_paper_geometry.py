@@ -143,3 +143,41 @@ def test_paper_geometry_full_scale_sampled(torch_dev):
     e = rel_l2(dh, dh_ref)
     say(f"gradient of the sampled wavelengths vs oracle adjoint {e:.2e}")
     assert e <= 1e-4
+
+
+def test_transform_1600_schedules_and_modes(torch_dev):
+    say("transform 1600: grouped schedule of two designs, recompute mode, tables, two lanes vs the base plan")
+    from paper_2604_02624_amd import dpx
+    torch = torch_dev
+    d, h, tau, _ = wk.paper_geometry(n_wl=4, layers=2)
+    d = dict(d, z_in=0.0)                       # the grouped schedule runs designs without an input gap
+    d2, h2, tau2, _ = wk.paper_geometry(n_wl=3, layers=1, cfg=7)
+    d2 = dict(d2, z_in=0.0)
+
+    def go(designs, hs, taus, **kw):
+        plan = dpx.Plan(designs, **kw)
+        hh = plan.pack_heights(hs)
+        I = plan.forward(hh)
+        _, g = plan.loss(I, plan.pack_images(taus))
+        dh = plan.backward(hh, None, g)
+        torch.cuda.synchronize()
+        out = (I.cpu().numpy(), dh.cpu().numpy(), plan.schedule())
+        plan.close()
+        return out
+
+    base = go([d], [h], [tau])
+    I_ref = o.forward(d, h, None, "fft")
+    assert max(rel_l2(base[0].reshape(I_ref.shape)[i], I_ref[i]) for i in range(4)) <= INT_TOL
+    # two designs: one grouped launch per pass and transform length
+    both = go([d, d2], [h, h2], [tau, tau2])
+    assert both[2] == 2
+    n1 = base[0].size
+    assert np.array_equal(both[0][:n1], base[0])
+    assert rel_l2(both[1][:h.size], base[1]) <= 1e-6
+    I2_ref = o.forward(d2, h2, None, "fft")
+    assert max(rel_l2(both[0][n1:].reshape(I2_ref.shape)[i], I2_ref[i]) for i in range(3)) <= INT_TOL
+    for kw in (dict(checkpoint_mode=1, wl_chunk=2), dict(transfer_table=2), dict(streams=2, wl_chunk=2)):
+        r = go([d], [h], [tau], **kw)
+        say(f"  {kw}: same intensities, gradient within {rel_l2(r[1], base[1]):.1e}")
+        assert np.array_equal(r[0], base[0])
+        assert rel_l2(r[1], base[1]) <= 1e-6
