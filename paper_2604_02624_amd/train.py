@@ -163,3 +163,45 @@ class Trainer:
     def close(self):
         for p in self._plans.values():
             p.close()
+
+
+def main(argv=None):
+    """Train one of the synthetic workloads for a few epochs and print the loss and PSNR:
+    python -m paper_2604_02624_amd.train --workload 3 --epochs 5 [--bits 8] [--misalign 40e-9 200e-9]"""
+    import argparse
+    import time
+    import torch
+    ap = argparse.ArgumentParser(description=main.__doc__.split("\n")[0])
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--bits", type=int, default=None, help="train with quantised heights")
+    ap.add_argument("--misalign", type=float, nargs=2, default=None, metavar=("D_XY", "D_Z"),
+                    help="vaccination: layer displacements U(+-D_XY) laterally, U(+-D_Z) axially")
+    ap.add_argument("--swap-after", type=int, default=0, help="channel swapping after this epoch (0: never)")
+    args = ap.parse_args(argv)
+    w = wk.make_workload(args.workload)
+    if len(w["designs"]) != 1:
+        raise SystemExit("training takes a workload of one design")
+    d, tau = w["designs"][0], w["targets"][0]
+    tr = Trainer(d, tau, d["h_max"], batch=args.batch, lr=args.lr, u_in=w["u_in"][0], bits=args.bits,
+                 misalign=tuple(args.misalign) if args.misalign else None)
+    rng = np.random.default_rng(0)
+    ps = tr.evaluate(bits=args.bits)
+    print(f"epoch 0: mean PSNR {ps.mean():.2f} dB", flush=True)
+    for e in range(1, args.epochs + 1):
+        t0 = time.perf_counter()
+        loss = tr.epoch(rng)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if args.swap_after and e == args.swap_after:
+            tr.swap_channels()
+        ps = tr.evaluate(bits=args.bits)
+        print(f"epoch {e}: loss {loss:.4e}, mean PSNR {ps.mean():.2f} dB (min {ps.min():.2f}), "
+              f"{dt * 1e3:.1f} ms", flush=True)
+    tr.close()
+
+
+if __name__ == "__main__":
+    main()
