@@ -180,3 +180,35 @@ def test_axial_jitter_on_matrix_core_variant_matches_oracle(torch_dev):
     I, _, _ = run(torch_dev, d, w["h"][0], w["targets"][0], force_variant=4)
     I_ref = o.forward(d, w["h"][0], None, "fft")
     assert rel_l2(I.reshape(I_ref.shape), I_ref) <= INT_TOL
+
+
+def test_misaligned_large_workload_sampled(torch_dev):
+    say("large workload (4 layers 512x512, transform 1024, 4096 wavelengths) misaligned as in the "
+        "benchmark: sampled wavelengths vs the oracle")
+    from paper_2604_02624_amd import dpx, robustness
+    torch = torch_dev
+    w = wk.make_workload(4)
+    d0, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
+    lateral, axial = robustness.draw_layer_offsets(np.random.default_rng(1), d0["layers"], 40e-9, 200e-9)
+    s = o.gap_shifts_from_layer_offsets(lateral)
+    d = dict(d0, shift_x=s[:, 0], shift_y=s[:, 1], dz=o.gap_jitter_from_layer_offsets(axial))
+    plan = dpx.Plan([d])
+    hh = plan.pack_heights([h])
+    I = plan.forward(hh)
+    sample = [0, 2047, 4095]
+    seed = np.zeros_like(tau)
+    seed[sample] = np.random.default_rng(2).standard_normal((3,) + tau.shape[1:]).astype(np.float32) * 1e-3
+    dh = plan.backward(hh, None, plan.pack_images([seed]))
+    torch.cuda.synchronize()
+    I = I.cpu().numpy().reshape(tau.shape)
+    dh = dh.cpu().numpy().reshape(h.shape)
+    plan.close()
+    I_ref = o.forward(d, h, None, "fft", wavelengths=sample)
+    errs = [rel_l2(I[w_], I_ref[i]) for i, w_ in enumerate(sample)]
+    say(f"sampled wavelengths: rel L2 {max(errs):.2e}")
+    assert max(errs) <= INT_TOL
+    assert rel_l2(o.forward(d0, h, None, "fft", wavelengths=sample), I_ref) > 10 * INT_TOL
+    dh_ref = o.grad(d, h, None, seed[sample].astype(np.float64), "fft", wavelengths=sample)
+    e = rel_l2(dh, dh_ref)
+    say(f"gradient of the sampled wavelengths vs oracle adjoint {e:.2e}")
+    assert e <= 1e-4
