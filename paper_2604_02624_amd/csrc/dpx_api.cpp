@@ -1576,6 +1576,18 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
           DPX_TRY(forward_chunk(p, d, h, u_in, w0, wc, lane, ls, first_ev));
           first_ev = nullptr;
         }
+        if (c < d.lanes) {
+          // a lane's first chunk writes its dL/dh slots (later chunks add to them); when that
+          // chunk is the short last one, the slots it does not reach must still read as zero
+          const int used = (wc + d.w_per_block - 1) / d.w_per_block;
+          if (used < d.slots_per_lane) {
+            const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;
+            hipError_t e = dpx::launch_fill_zero(
+                d.dh_part + (static_cast<int64_t>(lane) * d.slots_per_lane + used) * per,
+                static_cast<int64_t>(d.slots_per_lane - used) * per, ls);
+            if (e != hipSuccess) return fail(DPX_E_DEVICE, "slot clearing launch failed: %s", hipGetErrorString(e));
+          }
+        }
         DPX_TRY(adjoint_chunk(p, d, h, dl_di, w0, wc, lane, c >= d.lanes, ls, first_ev));
       }
       DPX_TRY(join_lanes(p, d, s));
