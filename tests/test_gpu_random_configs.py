@@ -209,3 +209,42 @@ def test_random_multi_design_plan_matches_oracle(torch_dev, seed):
         assert max(errs) <= 1e-5, errs
         dh_ref = o.grad(d, h, None, gi.numpy().astype(np.float64), "fft")
         assert rel_l2(dhi.numpy(), dh_ref) <= 1e-4
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_rebinding_matches_fresh_plan(torch_dev, seed):
+    """dpx_plan_set_wavelengths on a random design and option set gives the bits of a plan
+    created with the new wavelengths."""
+    from paper_2604_02624_amd import dpx
+    torch = torch_dev
+    d, h, tau, u_in, opts = random_case(100 + seed)
+    if seed % 3 == 0 and not d.get("band_limited"):
+        opts = dict(opts, transfer_table=2) if d.get("shift_x") is None and d.get("dz") is None \
+            and not opts.get("small_path") else opts
+    if seed % 2 == 1:
+        opts = dict(opts, use_graph=True)
+    g = np.random.default_rng(seed)
+    wl2 = np.sort(g.uniform(0.45e-6, 0.75e-6, d["n_wl"]))
+    d2 = dict(d, wl=wl2, n_mat=wk.cauchy_index(wl2))
+    if d.get("kappa") is not None:
+        d2["kappa"] = g.uniform(0, 0.02, d["n_wl"])
+    say(f"seed {seed}: N={d['n']} pad={d['pad']} K={d['layers']} W={d['n_wl']} {opts}")
+    u = None if u_in is None else torch.view_as_real(torch.as_tensor(u_in)).reshape(-1).cuda()
+
+    def run(plan):
+        hh = plan.pack_heights([h])
+        I = plan.forward(hh, u)
+        _, gi = plan.loss(I, plan.pack_images([tau]))
+        dh = plan.backward(hh, u, gi)
+        torch.cuda.synchronize()
+        return I.cpu().numpy(), dh.cpu().numpy()
+
+    rebound = dpx.Plan([d], **opts)
+    run(rebound)
+    rebound.set_wavelengths(0, d2["wl"], d2["n_mat"], d2.get("kappa"))
+    a = run(rebound)
+    rebound.close()
+    fresh = dpx.Plan([d2], **opts)
+    b = run(fresh)
+    fresh.close()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
