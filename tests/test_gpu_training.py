@@ -230,3 +230,27 @@ def test_training_reduces_the_loss(torch_dev):
     h = tr.heights()
     assert h.min() >= 0.0 and h.max() <= d["h_max"]
     tr.close()
+
+
+def test_psnr_degenerate_images(torch_dev):
+    say("PSNR with zero images and zero targets vs the oracle's conventions")
+    from paper_2604_02624_amd import dpx
+    wl = np.array([500e-9, 560e-9, 620e-9, 680e-9])
+    d = wk.make_design(n=32, layers=1, wl=wl, n_mat=1.5, dx=300e-9, z=[5e-6], fov=8, pad=2)
+    plan = dpx.Plan([d])
+    g = np.random.default_rng(3)
+    tau = g.random((4, 8, 8)).astype(np.float32)
+    I = g.random((4, 8, 8)).astype(np.float32)
+    I[0] = 0.0                 # no light: the normalised image is zero
+    tau[1] = 0.0               # empty target: its peak is zero (PSNR -inf)
+    I[2] = 0.0
+    tau[2] = 0.0               # both empty: identical (PSNR +inf)
+    got = plan.psnr(plan.pack_images([I]), plan.pack_images([tau])).cpu().numpy()
+    with np.errstate(divide="ignore"):       # log10(0) of the empty target is the -inf expected
+        ref = o.psnr(I, tau)
+    say(f"gpu {got}, oracle {ref}")
+    assert np.array_equal(np.isposinf(got), np.isposinf(ref))
+    assert np.array_equal(np.isneginf(got), np.isneginf(ref))
+    fin = np.isfinite(ref)
+    np.testing.assert_allclose(got[fin], ref[fin], rtol=1e-12)
+    plan.close()
