@@ -6,7 +6,8 @@
  * optical information storage and image projection", Section 4 "Optical forward model",
  * Eq. 1, 2, 4, 5; problem statement in Section 2 and the Fig. 1 caption):
  *
- *   for every wavelength lambda_w of a design, starting from the input field u_in:
+ *   for every wavelength lambda_w of a design, starting from the input field u_in
+ *   (carried over the input gap z_in by the same propagation when the design has one):
  *     for layer l = 0 .. K-1:
  *       u <- u * t_l,   t_l = exp(-2 pi kappa h_l / lambda) exp(+j 2 pi (n - n_m) h_l / lambda)
  *       u <- P_l u      (Rayleigh-Sommerfeld propagation over the gap z[l], Eq. 4/5,
@@ -24,6 +25,12 @@
  *
  *   backward: dL/dh for every height of every layer given dL/dI (hand-written adjoint:
  *   conjugate transfer function, reverse transforms, d t / d h).
+ *
+ *   Variants of the propagation: a per-gap lateral translation and axial jitter
+ *   (dpx_plan_set_misalignment) and the band-limited transfer function (dpx_design.band_limited)
+ *   change H only.  Around the path: per-wavelength PSNR (dpx_psnr), one fused Adam step on the
+ *   sigmoid-bounded heights (dpx_adam_step), the phase bit-depth quantiser
+ *   (dpx_quantize_heights) and rebinding a plan to new wavelengths (dpx_plan_set_wavelengths).
  *
  * The +j sign of the transmission phase is the reading consistent with the exp(+j k r)
  * outgoing wave of Eq. 4 (the printed Eq. 1 carries -j; with kappa = 0 that is the same model
@@ -66,7 +73,8 @@ typedef enum dpx_status {
   DPX_E_ARG = 1,          /* invalid argument: null pointer, bad shape, misaligned buffer */
   DPX_E_UNSUPPORTED = 2,  /* valid but not built or not applicable: transform length pad*N
                              not in the table, a forced column variant not built for it, the
-                             grouped schedule asked for where it cannot run */
+                             grouped schedule asked for where it cannot run, a misalignment or
+                             band limit on a path that cannot apply it */
   DPX_E_NOMEM = 3,        /* device allocation failed or exceeds opts.max_workspace_bytes */
   DPX_E_DEVICE = 4,       /* a HIP runtime error (launch failure, earlier async fault) */
   DPX_E_STATE = 5         /* call order: store-mode backward without a matching forward */
