@@ -248,3 +248,73 @@ def test_random_rebinding_matches_fresh_plan(torch_dev, seed):
     b = run(fresh)
     fresh.close()
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+
+def random_large_case(seed):
+    """A random design on the long transforms (512, 1024, 1600) with the options they support."""
+    g = np.random.default_rng([260402624, 97, seed])
+    M = int(g.choice([512, 1024, 1600]))
+    pad = int(g.choice([1, 2])) if M <= 1024 else 2
+    N = M // pad
+    K = int(g.integers(1, 3))
+    W = int(g.integers(1, 4))
+    wl = np.sort(g.uniform(0.4e-6, 0.75e-6, W))
+    bin_ = int(g.choice([1, 2, 8]))
+    fov = int(g.integers(1, min(N, 256) // (2 * bin_) + 1)) * 2 * bin_
+    d = wk.make_design(n=N, layers=K, wl=wl, n_mat=wk.nbk7_index(wl), dx=0.2e-6,
+                       z=g.uniform(10e-6, 80e-6, K), fov=fov, bin_=bin_, pad=pad,
+                       kappa=(g.uniform(0, 0.01, W) if g.random() < 0.3 else None))
+    if g.random() < 0.4:
+        d["z_in"] = float(g.uniform(5e-6, 60e-6))
+    band = g.random() < 0.3
+    if band:
+        d["band_limited"] = True
+    if g.random() < 0.4:
+        d["dz"] = g.uniform(-0.3e-6, 0.3e-6, K)
+        if not band and M <= 1024:
+            d["shift_x"] = g.uniform(-2, 2, K) * d["dx"]
+            d["shift_y"] = g.uniform(-2, 2, K) * d["dx"]
+    h = (g.random((K, N, N)) * 1.2e-6).astype(np.float32)
+    tau = g.random((W, fov // bin_, fov // bin_)).astype(np.float32)
+    u_in = None
+    if g.random() < 0.3:
+        u_in = (g.standard_normal((N, N)) + 1j * g.standard_normal((N, N))).astype(np.complex64)
+    opts = {}
+    variants = [0, 1] if (band or M > 1024) else [0, 1, 2, 3]
+    if g.random() < 0.6:
+        opts["force_variant"] = int(g.choice(variants))
+    r = g.random()
+    if r < 0.25:
+        opts.update(checkpoint_mode=1, wl_chunk=int(g.integers(1, W + 1)))
+    elif r < 0.5 and W > 1:
+        opts.update(streams=2, wl_chunk=int(g.integers(1, W)))
+    if g.random() < 0.2 and not band and d.get("dz") is None:
+        opts["transfer_table"] = 2
+    if g.random() < 0.3:
+        opts["use_graph"] = True
+    return d, h, tau, u_in, opts
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_long_transform_matches_oracle(torch_dev, seed):
+    from paper_2604_02624_amd import dpx
+    torch = torch_dev
+    d, h, tau, u_in, opts = random_large_case(seed)
+    say(f"seed {seed}: M={d['n'] * d['pad']} pad={d['pad']} K={d['layers']} W={d['n_wl']} F={d['fov']} "
+        f"b={d['bin']} {[k for k in ('z_in', 'band_limited', 'dz', 'shift_x', 'kappa') if d.get(k) is not None]} "
+        f"u_in={u_in is not None} {opts}")
+    plan = dpx.Plan([d], **opts)
+    hh = plan.pack_heights([h])
+    u = None if u_in is None else torch.view_as_real(torch.as_tensor(u_in)).reshape(-1).cuda()
+    I = plan.forward(hh, u)
+    _, g = plan.loss(I, plan.pack_images([tau]))
+    dh = plan.backward(hh, u, g)
+    torch.cuda.synchronize()
+    I = I.cpu().numpy().reshape(tau.shape)
+    g = g.cpu().numpy().reshape(tau.shape)
+    dh = dh.cpu().numpy().reshape(h.shape)
+    plan.close()
+    I_ref = o.forward(d, h, u_in, "fft")
+    assert max(rel_l2(I[i], I_ref[i]) for i in range(d["n_wl"])) <= 1e-5
+    assert rel_l2(dh, o.grad(d, h, u_in, g.astype(np.float64), "fft")) <= 1e-4
