@@ -132,16 +132,18 @@ class Trainer:
         gaps = (None, None, None) if offsets is None else robustness.gap_offsets(*offsets)
         for p in self._plans.values():
             p.set_misalignment(0, *gaps)
-        hh = self.heights_used(bits)
-        out = []
-        for gi, g in enumerate(self.groups):
-            p = self.plan(gi)
-            I = p.forward(hh, self.u, self._I[len(g)])
-            out.append(p.psnr(I, self.tau[gi]))
-        if offsets is not None:
-            for p in self._plans.values():
-                p.set_misalignment(0)
-        return self.torch.cat(out).cpu().numpy()
+        try:
+            hh = self.heights_used(bits)
+            out = []
+            for gi, g in enumerate(self.groups):
+                p = self.plan(gi)
+                I = p.forward(hh, self.u, self._I[len(g)])
+                out.append(p.psnr(I, self.tau[gi]))
+            return self.torch.cat(out).cpu().numpy()
+        finally:
+            if offsets is not None:
+                for p in self._plans.values():
+                    p.set_misalignment(0)
 
     def swap_channels(self, psnr_per_wl=None) -> np.ndarray:
         """Dynamic channel swapping: reassign the targets by PSNR to the wavelengths from the
