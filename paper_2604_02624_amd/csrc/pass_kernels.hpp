@@ -314,9 +314,15 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
   const int wb = by * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
   const unsigned voff = static_cast<unsigned>((((FULL ? 0 : a.in_lo) + yy) * M + kx0 + cc) * 8);
+  // The plane's base address is the same in every lane; reading it through readfirstlane
+  // keeps the descriptor in scalar registers (a descriptor left in vector registers makes
+  // the compiler wrap every load in a loop over the distinct descriptors of the wavefront).
   auto plane = [&](int w) {
-    return __builtin_amdgcn_make_buffer_rsrc(a.spec + static_cast<size_t>(w) * N * M, 0,
-                                             N * M * 8, kBufferRsrcWord3);
+    const uint64_t base = reinterpret_cast<uint64_t>(a.spec + static_cast<size_t>(w) * N * M);
+    const uint64_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(base)));
+    const uint64_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(base >> 32)));
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>((hi << 32) | lo), 0, N * M * 8,
+                                             kBufferRsrcWord3);
   };
   // FULL: the pass reads and keeps every aperture row (all passes but the first adjoint and
   // the last forward one), so the row-range tests drop out.
