@@ -111,7 +111,10 @@ typedef struct dpx_design {
 
 typedef struct dpx_opts {
   int32_t checkpoint_mode;  /* 0: forward stores the field after every transmission
-                               (K*W*N*N complex per design) for the backward;
+                               ((K-1)*W*N*N complex per design, K*W*N*N with an input gap
+                               z_in > 0: without one, the field after the first layer is
+                               u_in t_0(h), which the backward rebuilds from u_in and h) for
+                               the backward;
                                1: backward recomputes the forward chunk by chunk */
   int32_t wl_chunk;         /* wavelengths per chunk (0 = automatic) */
   int32_t use_graph;        /* nonzero: the first dpx_forward / dpx_loss / dpx_backward with a

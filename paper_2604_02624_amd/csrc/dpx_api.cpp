@@ -66,6 +66,9 @@ struct Design {
   int row_group;     // rows per row-pass block
   int col_variant;   // column-pass kernel variant
   bool lds = false;  // forward and adjoint as one LDS-resident launch each
+  // 1: the input field meets layer 0 directly, so its field after the first transmission,
+  // u_in t_0(h), is rebuilt by the last adjoint pass and gets no checkpoint slab
+  int ck_first = 0;
   // transfer-function tables: one [W][M/2+1][M/2+1] table per distinct gap; zslot[l] is the
   // table of layer l's gap (empty: H is evaluated in the column pass)
   int nzslots = 0;
@@ -305,8 +308,9 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
   const int ck_w = (o.checkpoint_mode == 1) ? d.lanes * d.wl_chunk : d.W;
   const int of_w = ck_w;
+  d.ck_first = (src.z_in == 0.0 && !d.lds) ? 1 : 0;
   d.bytes = static_cast<int64_t>(d.lanes) * d.wl_chunk * d.N * d.M * 8  // spec
-            + static_cast<int64_t>(d.K) * ck_w * nn * 8       // checkpoints
+            + static_cast<int64_t>(d.K - d.ck_first) * ck_w * nn * 8  // checkpoints
             + static_cast<int64_t>(of_w) * d.F * d.F * 8      // output field
             + static_cast<int64_t>(d.nslots) * d.K * nn * 4   // dL/dh partials
             + static_cast<int64_t>(d.W) * 8                   // per-wavelength loss
@@ -390,12 +394,13 @@ RowArgs row_args(const dpx_plan* p, const Design& d, int w0, int wc, int lane) {
   a.chunk_base = lane * d.slots_per_lane;
   a.spec = spec_of_lane(d, lane);
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
+  a.ckpt_first = d.ck_first;
   if (p->opts.checkpoint_mode == 1) {
-    a.ckpt = d.ckpt + static_cast<int64_t>(lane) * d.K * d.wl_chunk * nn;
+    a.ckpt = d.ckpt ? d.ckpt + static_cast<int64_t>(lane) * (d.K - d.ck_first) * d.wl_chunk * nn : nullptr;
     a.ckpt_w_stride = d.wl_chunk;
     a.ofov = d.ofov + static_cast<int64_t>(lane) * d.wl_chunk * d.F * d.F;
   } else {
-    a.ckpt = d.ckpt + w0 * nn;
+    a.ckpt = d.ckpt ? d.ckpt + w0 * nn : nullptr;
     a.ckpt_w_stride = d.W;
     a.ofov = d.ofov + static_cast<int64_t>(w0) * d.F * d.F;
   }
@@ -432,9 +437,14 @@ double row_flops(const Design& d, int mode, int wc, int rows) {
     case dpx::ROW_ADJ_SEED: return static_cast<double>(wc) * rows * per_row_fft;
     case dpx::ROW_ADJ_MID: return static_cast<double>(wc) * rows * (2 * per_row_fft + 12.0 * d.N);
     case dpx::ROW_ADJ_LAST: return static_cast<double>(wc) * rows * (per_row_fft + 6.0 * d.N);
+    case dpx::ROW_ADJ_LAST_U: return static_cast<double>(wc) * rows * (per_row_fft + 12.0 * d.N);
     default: return 0.0;
   }
 }
+
+// the last adjoint row pass: rebuilding layer 0's field from u_in and h when it has no
+// checkpoint slab
+int adj_last_mode(const Design& d) { return d.ck_first ? dpx::ROW_ADJ_LAST_U : dpx::ROW_ADJ_LAST; }
 
 // algorithmic bytes of one row-pass launch (every operand read or written once)
 int64_t row_bytes(const Design& d, int mode, int wc, int nwb, bool accumulate, bool has_u) {
@@ -443,12 +453,15 @@ int64_t row_bytes(const Design& d, int mode, int wc, int nwb, bool accumulate, b
   const int64_t fov = static_cast<int64_t>(d.F) * d.F * 8;
   const int64_t part = nwb * nn * 4 * (accumulate ? 2 : 1);
   switch (mode) {
-    case dpx::ROW_FWD_FIRST: return wc * (d.N * row + 8 * nn) + 4 * nn + (has_u ? 8 * nn : 0);
+    // the first pass stores no checkpoint (layer 0's is rebuilt, or the pass only carries the
+    // input plane to an input gap, reading no heights)
+    case dpx::ROW_FWD_FIRST: return wc * d.N * row + (d.z_in > 0.0 ? 0 : 4 * nn) + (has_u ? 8 * nn : 0);
     case dpx::ROW_FWD_MID: return wc * (2 * d.N * row + 8 * nn) + 4 * nn;
     case dpx::ROW_FWD_LAST: return wc * (d.F * row + fov);
     case dpx::ROW_ADJ_SEED: return wc * (fov + 4 * d.T * d.T + d.F * row);
     case dpx::ROW_ADJ_MID: return wc * (2 * d.N * row + 8 * nn) + 4 * nn + part;
     case dpx::ROW_ADJ_LAST: return wc * (d.N * row + 8 * nn) + 4 * nn + part;
+    case dpx::ROW_ADJ_LAST_U: return wc * d.N * row + 4 * nn + part + (has_u ? 8 * nn : 0);
     default: return 0;
   }
 }
@@ -459,7 +472,7 @@ dpx_status run_row(dpx_plan* p, const Design& d, int mode, RowArgs a, int row_lo
   const int rg = dpx::row_rows_per_block(d.M, mode);
   const int nrb = (row_hi - row_lo + rg - 1) / rg;
   const int nwb = (a.w_count + d.w_per_block - 1) / d.w_per_block;
-  TimedLaunch t{DPX_PASS_ROW_FWD_FIRST + mode, nullptr, nullptr,
+  TimedLaunch t{dpx::row_pass_kind(mode), nullptr, nullptr,
                 row_bytes(d, mode, a.w_count, nwb, a.accumulate != 0, a.u_in != nullptr),
                 row_flops(d, mode, a.w_count, row_hi - row_lo)};
   DPX_TRY(timer_begin(p, s, t));
@@ -549,10 +562,11 @@ dpx_status forward_chunk(dpx_plan* p, const Design& d, const float* h, const flo
     a.h = h + h_off_layer(d, 0);
     DPX_TRY(run_row(p, d, dpx::ROW_FWD_MID, a, 0, d.N, s));
   } else {
-    a.store_ckpt = 1;
+    a.store_ckpt = d.ck_first ? 0 : 1;
     a.h = h + h_off_layer(d, 0);
     DPX_TRY(run_row(p, d, dpx::ROW_FWD_FIRST, a, 0, d.N, s));
     if (after_first) DPX_HIP(hipEventRecord(after_first, s));
+    a.store_ckpt = 1;
   }
   for (int l = 0; l < d.K; ++l) {
     const bool last = (l == d.K - 1);
@@ -570,11 +584,12 @@ dpx_status forward_chunk(dpx_plan* p, const Design& d, const float* h, const flo
 
 // adjoint over one chunk on lane `lane`; dL/dh partials go to the lane's own slots, added to
 // what the lane's earlier chunks left there when `accumulate` is set
-dpx_status adjoint_chunk(dpx_plan* p, const Design& d, const float* h, const float* dl_di,
+dpx_status adjoint_chunk(dpx_plan* p, const Design& d, const float* h, const float* u_in, const float* dl_di,
                          int w0, int wc, int lane, bool accumulate, hipStream_t s,
                          hipEvent_t after_first) {
   const int fo = (d.N - d.F) / 2;
   RowArgs a = row_args(p, d, w0, wc, lane);
+  a.u_in = u_in ? reinterpret_cast<const float2*>(u_in) + d.u_off : nullptr;  // rebuilt layer 0
   a.dl_di = dl_di + d.img_off;
   a.store_ckpt = 0;
   a.accumulate = accumulate ? 1 : 0;
@@ -585,7 +600,7 @@ dpx_status adjoint_chunk(dpx_plan* p, const Design& d, const float* h, const flo
     DPX_TRY(run_col(p, d, lane, l, true, w0, wc, first ? fo : 0, first ? fo + d.F : d.N, 0, d.N, s));
     a.layer = l;
     a.h = h + h_off_layer(d, l);
-    DPX_TRY(run_row(p, d, l > 0 ? dpx::ROW_ADJ_MID : dpx::ROW_ADJ_LAST, a, 0, d.N, s));
+    DPX_TRY(run_row(p, d, l > 0 ? dpx::ROW_ADJ_MID : adj_last_mode(d), a, 0, d.N, s));
   }
   return DPX_OK;
 }
@@ -656,7 +671,7 @@ void add_row_position(dpx_plan* p, const std::vector<RowItem>& items, std::vecto
       const Design& d = p->designs[it.design];
       dpx::RowTask t{};
       t.a = row_args(p, d, 0, d.W, 0);
-      t.a.store_ckpt = (it.mode == dpx::ROW_FWD_FIRST || it.mode == dpx::ROW_FWD_MID) ? 1 : 0;
+      t.a.store_ckpt = (it.mode == dpx::ROW_FWD_MID || (it.mode == dpx::ROW_FWD_FIRST && !d.ck_first)) ? 1 : 0;
       t.a.accumulate = 0;
       t.a.layer = it.layer;
       t.a.row_lo = it.row_lo;
@@ -672,7 +687,8 @@ void add_row_position(dpx_plan* p, const std::vector<RowItem>& items, std::vecto
       nb.push_back(t.nblocks);
       al.push_back(1);
       by.push_back(row_bytes(d, it.mode, d.W, nwb, false, false));
-      ub.push_back(it.mode == dpx::ROW_FWD_FIRST ? 8 * static_cast<int64_t>(d.N) * d.N : 0);
+      const bool reads_u = it.mode == dpx::ROW_FWD_FIRST || it.mode == dpx::ROW_ADJ_LAST_U;
+      ub.push_back(reads_u ? 8 * static_cast<int64_t>(d.N) * d.N : 0);
       fl.push_back(row_flops(d, it.mode, d.W, it.row_hi - it.row_lo));
     }
     GroupLaunch proto{};
@@ -680,7 +696,7 @@ void add_row_position(dpx_plan* p, const std::vector<RowItem>& items, std::vecto
     proto.M = kv.first[0];
     proto.pad = kv.first[1];
     proto.mode = kv.first[2];
-    proto.pass = DPX_PASS_ROW_FWD_FIRST + proto.mode;
+    proto.pass = dpx::row_pass_kind(proto.mode);
     add_group(out, proto, tasks, nb, al, by, ub, fl, blob);
   }
 }
@@ -808,7 +824,7 @@ void build_group_lists(dpx_plan* p, const std::vector<int>& ids, std::vector<Gro
       const int l = d.K - 1 - k;
       const int fo = (d.N - d.F) / 2;
       cols.push_back({i, l, k == 0 ? fo : 0, k == 0 ? fo + d.F : d.N, 0, d.N});
-      rows.push_back({i, l > 0 ? dpx::ROW_ADJ_MID : dpx::ROW_ADJ_LAST, l, 0, d.N});
+      rows.push_back({i, l > 0 ? dpx::ROW_ADJ_MID : adj_last_mode(d), l, 0, d.N});
     }
     add_col_position(p, cols, true, bwd, blob);
     add_row_position(p, rows, bwd, blob);
@@ -1223,7 +1239,7 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     const int ck_w = (o.checkpoint_mode == 1) ? d.lanes * d.wl_chunk : d.W;
     if ((st = dev_alloc(&d.d_wl, d.W * sizeof(WlConst), "wavelength table")) != DPX_OK) break;
     if ((st = dev_alloc(&d.spec, static_cast<int64_t>(d.lanes) * d.wl_chunk * d.N * d.M * 8, "spectra")) != DPX_OK) break;
-    if ((st = dev_alloc(&d.ckpt, static_cast<int64_t>(d.K) * ck_w * nn * 8, "checkpoints")) != DPX_OK) break;
+    if ((st = dev_alloc(&d.ckpt, static_cast<int64_t>(d.K - d.ck_first) * ck_w * nn * 8, "checkpoints")) != DPX_OK) break;
     if ((st = dev_alloc(&d.ofov, static_cast<int64_t>(ck_w) * d.F * d.F * 8, "output field")) != DPX_OK) break;
     if ((st = dev_alloc(&d.dh_part, static_cast<int64_t>(d.nslots) * d.K * nn * 4, "gradient partials")) != DPX_OK) break;
     if ((st = dev_alloc(&d.per_wl, d.W * 8, "per-wavelength loss")) != DPX_OK) break;
@@ -1588,7 +1604,7 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
             if (e != hipSuccess) return fail(DPX_E_DEVICE, "slot clearing launch failed: %s", hipGetErrorString(e));
           }
         }
-        DPX_TRY(adjoint_chunk(p, d, h, dl_di, w0, wc, lane, c >= d.lanes, ls, first_ev));
+        DPX_TRY(adjoint_chunk(p, d, h, u_in, dl_di, w0, wc, lane, c >= d.lanes, ls, first_ev));
       }
       DPX_TRY(join_lanes(p, d, s));
       const int64_t per = static_cast<int64_t>(d.K) * d.N * d.N;

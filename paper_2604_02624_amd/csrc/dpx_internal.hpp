@@ -26,7 +26,12 @@ enum RowMode : int {
   ROW_ADJ_SEED = 3,   // 2 dL/dI o on the field of view -> pad -> row FFT
   ROW_ADJ_MID = 4,    // row IFFT -> crop -> dL/dh_l partial -> * conj(t_l) -> pad -> row FFT
   ROW_ADJ_LAST = 5,   // row IFFT -> crop -> dL/dh_0 partial
+  ROW_ADJ_LAST_U = 6, // the same with the field after layer 0 rebuilt as u_in * t_0 (no
+                      // checkpoint slab for layer 0: the input meets layer 0 directly)
 };
+
+// timer kind (dpx_pass) of a row-pass mode
+constexpr int row_pass_kind(int mode) { return 2 + (mode == ROW_ADJ_LAST_U ? ROW_ADJ_LAST : mode); }
 
 // Threads per row-pass block: 512 (eight transforms of 1024) where the registers allow two
 // such blocks per CU next to their LDS, 256 for the register-heavy adjoint middle pass.
@@ -41,7 +46,8 @@ struct RowArgs {
   float2* spec;              // [wc][N][M] row-transformed planes of the current chunk
   const float* h;            // [N][N] heights of the layer used by this pass
   const float2* u_in;        // [N][N] or null (unit plane wave)
-  float2* ckpt;              // [K][wc][N][N] fields after each transmission (chunk-local w)
+  float2* ckpt;              // [K - ckpt_first][wc][N][N] fields after each transmission
+                             // (chunk-local w); slab 0 holds layer ckpt_first
   float2* ofov;              // [wc][F][F] output field on the field of view
   const float* dl_di;        // [W][T][T] (global w)
   float* dh_part;            // [nchunk][K][N][N] per-chunk dL/dh partial sums
@@ -57,6 +63,8 @@ struct RowArgs {
   int accumulate;            // dL/dh partials: add to the slot instead of overwriting it
   int no_layer;              // ROW_FWD_FIRST only: u_in passes unchanged (the input plane before
                              // an input gap: no transmission, h not read)
+  int ckpt_first;            // 1: layer 0 has no checkpoint slab (ROW_ADJ_LAST_U rebuilds
+                             // u_in t_0(h) from u_in and h)
 };
 
 struct ColArgs {

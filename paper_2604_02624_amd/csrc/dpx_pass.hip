@@ -33,6 +33,7 @@ hipError_t row_mode(int mode, const RowArgs& a, dim3 grid, hipStream_t s) {
     DPX_ROW(ROW_ADJ_SEED)
     DPX_ROW(ROW_ADJ_MID)
     DPX_ROW(ROW_ADJ_LAST)
+    DPX_ROW(ROW_ADJ_LAST_U)
 #undef DPX_ROW
     default: return hipErrorInvalidValue;
   }
@@ -50,6 +51,7 @@ hipError_t row_group_mode(int mode, const GroupArgs& g, hipStream_t s) {
     DPX_ROW(ROW_ADJ_SEED)
     DPX_ROW(ROW_ADJ_MID)
     DPX_ROW(ROW_ADJ_LAST)
+    DPX_ROW(ROW_ADJ_LAST_U)
 #undef DPX_ROW
     default: return hipErrorInvalidValue;
   }

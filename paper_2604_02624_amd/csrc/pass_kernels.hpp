@@ -77,7 +77,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 
   float hreg[EN];
   if constexpr (MODE == ROW_FWD_FIRST || MODE == ROW_FWD_MID || MODE == ROW_ADJ_MID ||
-                MODE == ROW_ADJ_LAST) {
+                MODE == ROW_ADJ_LAST || MODE == ROW_ADJ_LAST_U) {
     const bool read_h = MODE != ROW_FWD_FIRST || !a.no_layer;
 #pragma unroll
     for (int t = 0; t < EN; ++t) hreg[t] = read_h ? a.h[static_cast<size_t>(y) * N + j0 + P * t] : 0.f;
@@ -99,8 +99,8 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 #pragma unroll
         for (int t = 0; t < EN; ++t) reg[t] = cmul(uin[t], transmission(hreg[t], c));
       }
-      if (a.store_ckpt && active) {
-        float2* ck = a.ckpt + (static_cast<size_t>(a.layer) * a.ckpt_w_stride + wc) * nn +
+      if (a.store_ckpt && !a.ckpt_first && active) {
+        float2* ck = a.ckpt + (static_cast<size_t>(a.layer - a.ckpt_first) * a.ckpt_w_stride + wc) * nn +
                      static_cast<size_t>(y) * N;
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
@@ -124,7 +124,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 #pragma unroll
       for (int t = 0; t < EN; ++t) reg[t] = cmul(reg[t], transmission(hreg[t], c));
       if (a.store_ckpt && active) {
-        float2* ck = a.ckpt + (static_cast<size_t>(a.layer) * a.ckpt_w_stride + wc) * nn +
+        float2* ck = a.ckpt + (static_cast<size_t>(a.layer - a.ckpt_first) * a.ckpt_w_stride + wc) * nn +
                      static_cast<size_t>(y) * N;
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
@@ -179,7 +179,13 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
         for (int t = 0; t < E; ++t) dst[j0 + P * t] = reg[t];
       }
     }
-  } else {  // ROW_ADJ_MID, ROW_ADJ_LAST
+  } else {  // ROW_ADJ_MID, ROW_ADJ_LAST, ROW_ADJ_LAST_U
+    // ROW_ADJ_LAST_U: the input field meets the first layer directly, so the field after the
+    // first transmission is u_in t_0(h); the pass rebuilds it from the input and the heights
+    // with the same operations as the first forward pass (so the same bits) instead of
+    // reading back a stored copy.  u_in is read where it is used, not held in registers.
+    constexpr bool REBUILD = (MODE == ROW_ADJ_LAST_U);
+    const float2* urow = (REBUILD && a.u_in) ? a.u_in + static_cast<size_t>(y) * N : nullptr;
     float acc[EN];
 #pragma unroll
     for (int t = 0; t < EN; ++t) acc[t] = 0.f;
@@ -187,8 +193,9 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       const WlConst c = a.wl[w];
       const int wc = w - a.w_begin;
       float2* row = a.spec + wc * plane + static_cast<size_t>(y) * M;
-      const float2* ck = a.ckpt + (static_cast<size_t>(a.layer) * a.ckpt_w_stride + wc) * nn +
-                         static_cast<size_t>(y) * N;
+      const float2* ck = REBUILD ? nullptr
+                                 : a.ckpt + (static_cast<size_t>(a.layer - a.ckpt_first) * a.ckpt_w_stride + wc) * nn +
+                                       static_cast<size_t>(y) * N;
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
@@ -198,7 +205,13 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 #pragma unroll
       for (int t = 0; t < EN; ++t) {
         const float2 gv = reg[t];
-        const float2 v = ck[j0 + P * t];
+        float2 v;
+        if constexpr (REBUILD) {
+          const float2 u = urow ? urow[j0 + P * t] : make_float2(1.f, 0.f);
+          v = cmul(u, transmission(hreg[t], c));
+        } else {
+          v = ck[j0 + P * t];
+        }
         // conj(g) v; acc += -ct Im - ca Re
         const float re = fmaf(gv.x, v.x, gv.y * v.y);
         const float im = fmaf(gv.x, v.y, -(gv.y * v.x));

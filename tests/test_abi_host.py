@@ -50,8 +50,21 @@ def test_query_workspace_of_the_large_workload(lib):
     b = _query([d])
     N, M, K, W, F = 64, 128, 2, 6, 32
     spec = W * N * M * 8
-    ck = K * W * N * N * 8
+    ck = (K - 1) * W * N * N * 8            # layer 0's field is rebuilt from u_in and h
     assert b >= spec + ck + W * F * F * 8
+
+
+def test_query_checkpoint_slab_of_the_first_layer(lib):
+    """Without an input gap the field after the first layer is not stored (one slab of W N^2
+    complex less); with one it is, in store and recompute modes alike."""
+    d = wk.make_workload(1)["designs"][0]
+    N, W = d["n"], d["n_wl"]
+    gap = dict(d, z_in=10e-6)
+    assert _query([gap]) - _query([d]) == W * N * N * 8
+    rec = dict(checkpoint_mode=1, wl_chunk=2)
+    assert _query([gap], **rec) - _query([d], **rec) == 2 * N * N * 8
+    one = dict(d, layers=1, z=d["z"][:1])
+    assert _query([dict(one, z_in=10e-6)]) - _query([one]) == W * N * N * 8
 
 
 def test_query_store_vs_recompute_memory(lib):
@@ -59,7 +72,7 @@ def test_query_store_vs_recompute_memory(lib):
                        z=3e-5, fov=64)
     store = _query([d])
     rec = _query([d], checkpoint_mode=1, wl_chunk=64)
-    assert store > 32 * 2 ** 30            # 32 GiB of checkpoints alone
+    assert store > 32 * 2 ** 30            # 24 GiB of checkpoints and 16 GiB of spectra
     assert rec < 2 * 2 ** 30
     assert store < 288e9                    # fits one MI355X
     two = _query([d], streams=2)            # two lanes of quarter-size chunks: 8 GiB of spectra
