@@ -309,12 +309,14 @@ dpx_status dpx_adam_step(float* theta, float* h, const float* dl_dh, float* m, f
 typedef enum dpx_pass {
   DPX_PASS_COL_FWD = 0,       /* column pass with H (forward) */
   DPX_PASS_COL_ADJ = 1,       /* column pass with conj(H) (adjoint) */
-  DPX_PASS_ROW_FWD_FIRST = 2, /* u_in * t_0 -> row FFT */
+  DPX_PASS_ROW_FWD_FIRST = 2, /* u_in * t_0 -> row FFT (no checkpoint: see ROW_ADJ_LAST) */
   DPX_PASS_ROW_FWD_MID = 3,   /* row IFFT -> crop -> * t_l -> row FFT */
   DPX_PASS_ROW_FWD_LAST = 4,  /* row IFFT -> output field of view */
   DPX_PASS_ROW_ADJ_SEED = 5,  /* 2 dL/dI o -> row FFT */
   DPX_PASS_ROW_ADJ_MID = 6,   /* row IFFT -> dL/dh partial -> * conj(t_l) -> row FFT */
-  DPX_PASS_ROW_ADJ_LAST = 7,  /* row IFFT -> dL/dh partial (first layer) */
+  DPX_PASS_ROW_ADJ_LAST = 7,  /* row IFFT -> dL/dh partial (first layer; without an input
+                                 gap its field after the transmission, u_in * t_0, is rebuilt
+                                 from u_in and h instead of read back) */
   DPX_PASS_LDS_FWD = 8,       /* LDS-resident forward of a whole design (short transforms) */
   DPX_PASS_LDS_ADJ = 9,       /* LDS-resident adjoint of a whole design */
   DPX_PASS_COUNT = 10
