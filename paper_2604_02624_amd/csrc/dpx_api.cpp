@@ -244,18 +244,13 @@ void layout_design(const dpx_design& src, const dpx_opts& o, Design& d) {
   d.n_m = src.n_medium;
   d.z_in = src.z_in;
   d.band = src.band_limited != 0;
-  const int P = dpx::row_lanes_per_transform(d.M);
-  (void)P;
   d.row_group = dpx::row_rows_per_block(d.M, dpx::ROW_FWD_MID);
   const int row_blocks = (d.N + d.row_group - 1) / d.row_group;
   // wavelengths per chunk: everything at once unless asked otherwise (recompute mode
-  // defaults to chunks of 64)
-  // concurrent lanes: chunks of wavelengths on several streams, so that one chunk's column
-  // pass (arithmetic-bound) can run beside another chunk's row pass (memory-bound)
-  const int64_t work = static_cast<int64_t>(d.W) * d.N * d.M;
-  // (measured on the large workload: two lanes share the chip without shortening the step,
-  // so the automatic choice is one lane; more lanes remain available on request)
-  (void)work;
+  // defaults to chunks of 64).  Concurrent lanes run chunks of wavelengths on several
+  // streams, so that one chunk's column pass (arithmetic-bound) can run beside another
+  // chunk's row pass (memory-bound); measured on the large workload, two lanes share the chip
+  // without shortening the step, so the automatic choice is one lane (more on request).
   const int lanes_wanted = o.streams > 0 ? o.streams : 1;
   int chunk = o.wl_chunk > 0 ? o.wl_chunk
                              : (o.checkpoint_mode == 1 ? 64 : (d.W + 2 * lanes_wanted - 1) / (2 * lanes_wanted));
@@ -925,7 +920,6 @@ dpx_status run_lds(dpx_plan* p, const Design& d, bool adjoint, const float* h, c
   a.bin = d.b;
   a.W = d.W;
   // algorithmic work: every pass of the multi-kernel path, without its spectrum traffic
-  const int fo = (d.N - d.F) / 2;
   double flops = 0.0;
   int64_t bytes = static_cast<int64_t>(d.K) * d.N * d.N * 4 + (u_in ? 8LL * d.N * d.N : 0);
   const int64_t nn = static_cast<int64_t>(d.N) * d.N;
@@ -938,7 +932,6 @@ dpx_status run_lds(dpx_plan* p, const Design& d, bool adjoint, const float* h, c
              row_flops(d, dpx::ROW_ADJ_LAST, d.W, d.N) + d.K * col_flops(d, d.W);
     bytes += static_cast<int64_t>(d.W) * (d.K * nn * 8 + d.F * d.F * 8 + d.T * d.T * 4 + d.K * nn * 4);
   }
-  (void)fo;
   TimedLaunch t{adjoint ? DPX_PASS_LDS_ADJ : DPX_PASS_LDS_FWD, nullptr, nullptr, bytes, flops};
   DPX_TRY(timer_begin(p, s, t));
   hipError_t e = dpx::launch_lds(d.M, d.pad, adjoint, a, s);
