@@ -338,6 +338,8 @@ class Plan:
     def backward(self, h, u_in, dl_di, out=None, stream=None):
         import torch
         self._check_dev(h, self.h_count, torch.float32, "h")
+        if u_in is not None:
+            self._check_dev(u_in, 2 * self.u_count, torch.float32, "u_in")
         self._check_dev(dl_di, self.img_count, torch.float32, "dl_di")
         if out is None:
             out = torch.empty(self.h_count, dtype=torch.float32, device=h.device)

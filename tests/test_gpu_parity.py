@@ -543,6 +543,8 @@ def test_error_paths(torch_dev):
     plan.backward(h, None, g)
     with pytest.raises(ValueError):
         plan.forward(h[:-1].contiguous())
+    with pytest.raises(ValueError):       # an input field of the wrong size, caught by the binding
+        plan.backward(h, torch_dev.zeros(2 * plan.u_count - 2, device="cuda"), g)
     lib = plan.lib
     assert lib.dpx_forward(plan._h, None, None, dpx._ptr(I), None) == dpx.DPX_E_ARG
     with pytest.raises(dpx.DpxError) as e:
