@@ -77,7 +77,8 @@ typedef enum dpx_status {
                              band limit on a path that cannot apply it */
   DPX_E_NOMEM = 3,        /* device allocation failed or exceeds opts.max_workspace_bytes */
   DPX_E_DEVICE = 4,       /* a HIP runtime error (launch failure, earlier async fault) */
-  DPX_E_STATE = 5         /* call order: store-mode backward without a matching forward */
+  DPX_E_STATE = 5,        /* call order: store-mode backward without a matching forward */
+  DPX_E_NONFINITE = 6     /* opts.check_finite: an output holds a NaN or an infinity */
 } dpx_status;
 
 /* One independent design (paper Section 2: K layers of N x N features, N_w wavelengths,
@@ -171,7 +172,12 @@ typedef struct dpx_opts {
                                wavelength) are one launch each.  Same bits either way.  Not the
                                default: measured on MI355X it ties the multi-pass kernels on
                                a few wavelengths and is slower on many (one block per CU). */
-  int32_t reserved;
+  int32_t check_finite;     /* nonzero (a debugging aid): dpx_forward, dpx_loss and
+                               dpx_backward count the NaN and infinite values in what they
+                               wrote (intensities; loss and dL/dI; dL/dh), wait for the stream
+                               and return DPX_E_NONFINITE naming the output and the count.
+                               Such calls synchronise, so they cannot be stream-captured.
+                               0: no scan, no synchronisation. */
 } dpx_opts;
 
 /* Offsets (in elements of the buffer's type) of one design inside the packed buffers. */

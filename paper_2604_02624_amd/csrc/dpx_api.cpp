@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <limits>
 #include <array>
 #include <map>
@@ -149,6 +150,9 @@ struct dpx_plan {
   std::vector<GroupLaunch> g_loss;
   void* d_tasks = nullptr;
   const dpx::LossTask* d_loss_tasks = nullptr;
+  // opts.check_finite: counters of non-finite output values, one per output of a call
+  unsigned* d_nonfinite = nullptr;
+  int64_t h_total = 0, img_total = 0;
   int64_t bytes = 0;
   bool fwd_valid = false;
   const float* last_h = nullptr;
@@ -372,6 +376,40 @@ dpx_status sticky_check() {
 
 float2* spec_of_lane(const Design& d, int lane) {
   return d.spec + static_cast<int64_t>(lane) * d.wl_chunk * d.N * d.M;
+}
+
+// opts.check_finite: counts the NaN and infinite values of a call's outputs on its stream,
+// waits for them and reports the first output that holds any
+struct OutputSpan {
+  const void* p;
+  int64_t n;
+  bool f64;
+  const char* name;
+};
+
+dpx_status check_outputs(dpx_plan* p, std::initializer_list<OutputSpan> outs, hipStream_t s) {
+  if (!p->opts.check_finite) return DPX_OK;
+  const int k = static_cast<int>(outs.size());
+  hipError_t e = dpx::launch_fill_zero(reinterpret_cast<float*>(p->d_nonfinite), k, s);
+  int i = 0;
+  for (const auto& o : outs) {
+    if (e == hipSuccess && o.p)
+      e = o.f64 ? dpx::launch_count_nonfinite(static_cast<const double*>(o.p), o.n, p->d_nonfinite + i, s)
+                : dpx::launch_count_nonfinite(static_cast<const float*>(o.p), o.n, p->d_nonfinite + i, s);
+    ++i;
+  }
+  unsigned counts[8] = {};
+  if (e == hipSuccess) e = hipMemcpyAsync(counts, p->d_nonfinite, k * sizeof(unsigned), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "non-finite scan failed: %s", hipGetErrorString(e));
+  i = 0;
+  for (const auto& o : outs) {
+    if (counts[i])
+      return fail(DPX_E_NONFINITE, "%s holds %u NaN or infinite value(s) of %lld", o.name, counts[i],
+                  static_cast<long long>(o.n));
+    ++i;
+  }
+  return DPX_OK;
 }
 
 // launch arguments for chunk [w0, w0 + wc) running on lane `lane`
@@ -1262,6 +1300,11 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
       p->bytes += tb;
     }
   }
+  for (const auto& d : p->designs) {
+    p->h_total += static_cast<int64_t>(d.K) * d.N * d.N;
+    p->img_total += static_cast<int64_t>(d.W) * d.T * d.T;
+  }
+  if (st == DPX_OK && o.check_finite) st = dev_alloc(&p->d_nonfinite, 256, "non-finite counters");
   // grouped schedule: asked for, or automatic for several designs whose wavelengths are not
   // split over chunk lanes (the grouped lists of up to four design partitions then run side by
   // side, like single designs)
@@ -1369,6 +1412,7 @@ dpx_status dpx_plan_destroy(dpx_plan* p) {
   for (auto& kv : p->twiddles) hipFree(kv.second);
   for (auto& kv : p->dft) hipFree(kv.second);
   if (p->d_tasks) hipFree(p->d_tasks);
+  if (p->d_nonfinite) hipFree(p->d_nonfinite);
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->gstream) (void)hipStreamDestroy(p->gstream);
   if (p->ev_gin) (void)hipEventDestroy(p->ev_gin);
@@ -1514,6 +1558,7 @@ dpx_status dpx_forward(dpx_plan* p, const float* h, const float* u_in, float* in
   p->fwd_valid = (p->opts.checkpoint_mode == 0);
   p->last_h = h;
   p->last_u = u_in;
+  DPX_TRY(check_outputs(p, {{intensity, p->img_total, false, "intensity"}}, caller));
   return ok();
 }
 
@@ -1545,6 +1590,10 @@ dpx_status dpx_loss(dpx_plan* p, const float* intensity, const float* target, do
     });
   };
   DPX_TRY(run_graph_or_eager(p, graph_key(2, intensity, target, loss, dl_di), caller, enqueue));
+  DPX_TRY(check_outputs(p,
+                        {{loss, static_cast<int64_t>(p->designs.size()), true, "loss"},
+                         {dl_di, p->img_total, false, "dl_di"}},
+                        caller));
   return ok();
 }
 
@@ -1607,6 +1656,7 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
     });
   };
   DPX_TRY(run_graph_or_eager(p, graph_key(3, h, u_in, dl_di, dl_dh), caller, enqueue));
+  DPX_TRY(check_outputs(p, {{dl_dh, p->h_total, false, "dl_dh"}}, caller));
   return ok();
 }
 

@@ -252,6 +252,9 @@ hipError_t launch_loss_sum(const double* per_wl, double* loss, int W, hipStream_
 hipError_t launch_dh_reduce(const float* part, float* dh, int nchunk, int64_t per_chunk,
                             hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+// adds the number of NaN and infinite values among x[0..n) to *count (integer atomics)
+hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned* count, hipStream_t s);
+hipError_t launch_count_nonfinite(const double* x, int64_t n, unsigned* count, hipStream_t s);
 
 // Adam on theta with h = h_max sigmoid(theta) (see adam_sigmoid_kernel)
 struct AdamArgs {

@@ -1,6 +1,7 @@
 // HIP kernels for gfx950 that do not depend on the transform length (intensity binning, loss,
 // gradient reduction), host-side tables (stage twiddles, DFT matrices), and the dispatch of
 // the per-length pass launchers (dpx_pass.hip, one translation unit per length).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -220,6 +221,18 @@ psnr_kernel(const float* __restrict__ I, const float* __restrict__ tau, double* 
 __global__ void fill_zero_kernel(float* p, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
+}
+
+// Counts the NaN and infinite values of x (grid-stride); one integer atomic per lane that
+// found any, so the count is exact and independent of the launch shape.
+template <typename T>
+__global__ void __launch_bounds__(256) count_nonfinite_kernel(const T* __restrict__ x, int64_t n,
+                                                              unsigned* __restrict__ count) {
+  unsigned c = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    c += isfinite(x[i]) ? 0u : 1u;
+  if (c) atomicAdd(count, c);
 }
 
 
@@ -497,6 +510,21 @@ hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
   const int th = 256;
   fill_zero_kernel<<<static_cast<unsigned>((n + th - 1) / th), th, 0, s>>>(p, n);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t count_nonfinite(const T* x, int64_t n, unsigned* count, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int th = 256;
+  const int64_t blocks = std::min<int64_t>((n + th - 1) / th, 4096);
+  count_nonfinite_kernel<T><<<static_cast<unsigned>(blocks), th, 0, s>>>(x, n, count);
+  return hipGetLastError();
+}
+hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned* count, hipStream_t s) {
+  return count_nonfinite(x, n, count, s);
+}
+hipError_t launch_count_nonfinite(const double* x, int64_t n, unsigned* count, hipStream_t s) {
+  return count_nonfinite(x, n, count, s);
 }
 
 }  // namespace dpx

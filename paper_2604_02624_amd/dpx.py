@@ -15,9 +15,9 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libdpx.so")
 
-DPX_OK, DPX_E_ARG, DPX_E_UNSUPPORTED, DPX_E_NOMEM, DPX_E_DEVICE, DPX_E_STATE = range(6)
+DPX_OK, DPX_E_ARG, DPX_E_UNSUPPORTED, DPX_E_NOMEM, DPX_E_DEVICE, DPX_E_STATE, DPX_E_NONFINITE = range(7)
 STATUS_NAMES = {0: "DPX_OK", 1: "DPX_E_ARG", 2: "DPX_E_UNSUPPORTED", 3: "DPX_E_NOMEM",
-                4: "DPX_E_DEVICE", 5: "DPX_E_STATE"}
+                4: "DPX_E_DEVICE", 5: "DPX_E_STATE", 6: "DPX_E_NONFINITE"}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -36,7 +36,7 @@ class COpts(ctypes.Structure):
                 ("force_variant", ctypes.c_int32), ("transfer_table", ctypes.c_int32),
                 ("max_workspace_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("small_path", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32)]
 
 
 class CLayout(ctypes.Structure):
@@ -142,7 +142,8 @@ def _c_designs(designs):
 
 
 def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
-          autotune=0, streams=0, use_graph=0, schedule=0, transfer_table=0, small_path=0):
+          autotune=0, streams=0, use_graph=0, schedule=0, transfer_table=0, small_path=0,
+          check_finite=0):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
@@ -155,6 +156,7 @@ def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_by
     o.schedule = int(schedule)
     o.transfer_table = int(transfer_table)
     o.small_path = int(small_path)
+    o.check_finite = int(check_finite)
     return o
 
 
@@ -191,7 +193,7 @@ class Plan:
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
                  force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False,
                  streams: int = 0, use_graph: bool = False, schedule: int = 0,
-                 transfer_table: int = 0, small_path: int = 0):
+                 transfer_table: int = 0, small_path: int = 0, check_finite: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
@@ -199,7 +201,7 @@ class Plan:
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
         o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune,
-                  streams, use_graph, schedule, transfer_table, small_path)
+                  streams, use_graph, schedule, transfer_table, small_path, check_finite)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))

@@ -34,6 +34,17 @@ def test_header_declares_the_entry_points():
         assert f in names
 
 
+def test_binding_matches_the_header_constants_and_option_layout():
+    """Status codes and dpx_opts field order as the header declares them."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    codes = dict((name, int(v)) for name, v in re.findall(r"\b(DPX_(?:OK|E_[A-Z]+))\s*=\s*(\d+)", src))
+    assert codes == {name: code for code, name in dpx.STATUS_NAMES.items()}
+    body = re.search(r"typedef struct dpx_opts \{(.*?)\} dpx_opts;", src, flags=re.S).group(1)
+    fields = re.findall(r"\b(int32_t|int64_t)\s+(\w+);", body)
+    ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64}
+    assert [(n, ctype[t]) for t, n in fields] == list(dpx.COpts._fields_)
+
+
 def test_library_exports_every_declared_symbol(lib):
     raw = ctypes.CDLL(dpx.LIB_PATH)
     for name in declared_functions():

@@ -557,6 +557,47 @@ def test_error_paths(torch_dev):
     torch_dev.cuda.synchronize()
 
 
+def test_check_finite_option(torch_dev):
+    say("opts.check_finite: same bits on finite data; NaN heights, an infinite target and NaN dL/dI reported")
+    from paper_2604_02624_amd import dpx
+    torch = torch_dev
+    w = wk.make_workload(2)
+    d, h_np, tau_np = w["designs"][0], w["h"][0], w["targets"][0]
+    plain = dpx.Plan([d])
+    chk = dpx.Plan([d], check_finite=True)
+    out = []
+    for plan in (plain, chk):
+        h = plan.pack_heights([h_np])
+        I = plan.forward(h)
+        L, g = plan.loss(I, plan.pack_images([tau_np]))
+        dh = plan.backward(h, None, g)
+        out.append((I.cpu(), L.cpu(), g.cpu(), dh.cpu()))
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+    h = chk.pack_heights([h_np])
+    bad_h = h.clone()
+    bad_h[5] = float("nan")
+    with pytest.raises(dpx.DpxError) as e:
+        chk.forward(bad_h)
+    assert e.value.status == dpx.DPX_E_NONFINITE and "intensity" in str(e.value)
+    I = chk.forward(h)
+    bad_tau = chk.pack_images([tau_np])
+    bad_tau[3] = float("inf")
+    with pytest.raises(dpx.DpxError) as e:
+        chk.loss(I, bad_tau)
+    assert e.value.status == dpx.DPX_E_NONFINITE
+    L, g = chk.loss(I, chk.pack_images([tau_np]))
+    g[7] = float("nan")
+    with pytest.raises(dpx.DpxError) as e:
+        chk.backward(h, None, g)
+    assert e.value.status == dpx.DPX_E_NONFINITE and "dl_dh" in str(e.value)
+    # the plan keeps working after a reported output
+    L, g = chk.loss(I, chk.pack_images([tau_np]))
+    assert torch.equal(chk.backward(h, None, g).cpu(), out[0][3])
+    plain.close()
+    chk.close()
+
+
 def test_autograd_function(torch_dev):
     say("torch.autograd.Function wrapper")
     from paper_2604_02624_amd import dpx
