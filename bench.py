@@ -149,7 +149,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--checkpoint-mode", type=int, default=0, choices=[0, 1])
     ap.add_argument("--wl-chunk", type=int, default=0)
@@ -165,7 +165,7 @@ def main():
                          "direct step after the timed region)")
     ap.add_argument("--variant", type=int, default=-1, help="column-pass variant (-1 automatic)")
     ap.add_argument("--autotune", action="store_true", help="time column-pass variants at plan creation")
-    ap.add_argument("--reps", type=int, default=10,
+    ap.add_argument("--reps", type=int, default=20,
                     help="single steps and forward calls timed one by one after the timed region "
                          "(median, p10, p90); 0 skips them")
     ap.add_argument("--train-epochs", type=int, default=1,
