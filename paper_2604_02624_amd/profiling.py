@@ -22,9 +22,11 @@ import sys
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# the sources that define the pass kernels (their code, launch shapes and argument structs); a
+# traffic record taken on other versions of them no longer describes the kernel
 KERNEL_SOURCES = ["paper_2604_02624_amd/csrc/pass_kernels.hpp", "paper_2604_02624_amd/csrc/dpx_pass.hip",
-                  "paper_2604_02624_amd/csrc/dpx_kernels.hip", "paper_2604_02624_amd/csrc/fft.hpp",
-                  "paper_2604_02624_amd/csrc/phase.hpp"]
+                  "paper_2604_02624_amd/csrc/fft.hpp", "paper_2604_02624_amd/csrc/phase.hpp",
+                  "paper_2604_02624_amd/csrc/dpx_internal.hpp"]
 
 
 def kernel_source_sha() -> str:
