@@ -247,7 +247,8 @@ dpx_status dpx_plan_set_wavelengths(dpx_plan* plan, int32_t design, const double
  * backward must see the same misalignment.  Errors: DPX_E_ARG for a bad index or count, a
  * non-finite value or a negative gap; DPX_E_UNSUPPORTED for a non-zero misalignment on a design
  * that runs the grouped schedule, the LDS-resident path or transfer tables, or a lateral one
- * with the matrix-core column variant.  On error the plan is unchanged. */
+ * with the matrix-core column variant or the band-limited spectrum.  On error the plan is
+ * unchanged. */
 dpx_status dpx_plan_set_misalignment(dpx_plan* plan, int32_t design, const double* dz,
                                      const double* shift_x, const double* shift_y, int32_t n_gaps);
 

@@ -1493,8 +1493,6 @@ dpx_status dpx_plan_set_misalignment(dpx_plan* p, int32_t i, const double* dz, c
     return fail(DPX_E_UNSUPPORTED, "design %d: the matrix-core column variant has no lateral translation", i);
   if (lateral && d.band)
     return fail(DPX_E_UNSUPPORTED, "design %d: no lateral translation with the band-limited spectrum", i);
-  if (lateral && !dpx::col_translation_supported(d.M))
-    return fail(DPX_E_UNSUPPORTED, "design %d: no lateral translation at transform length %d", i, d.M);
   // captured graphs hold the old kernel arguments
   if (!p->graphs.empty()) {
     if (hipDeviceSynchronize() != hipSuccess) return fail(DPX_E_DEVICE, "device synchronisation failed");

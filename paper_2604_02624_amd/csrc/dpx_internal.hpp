@@ -74,8 +74,6 @@ struct ColArgs {
   double zrev;               // z / (M dx): revolutions per unit of sqrt(q)
   double sx, sy;             // lateral translation of the gap / (M dx): revolutions per signed
                              // frequency index (0, 0 unless the plan has a misalignment)
-  float2 ystep;              // exp(-i 2 pi P sy), P = rows between a lane's registers (set by
-                             // the launcher of a translated gap)
   int band_limited;          // band-limited angular spectrum (per-element H evaluation only)
   int n;
   int in_lo, in_hi;          // rows holding non-zero input (others read as zero)
@@ -238,7 +236,6 @@ bool col_variant_supported(int M, int pad, int variant);
 void build_dft_table(int M, int pad, std::vector<float2>& out);
 extern const char* const kColVariantNames[kColVariants];
 int default_col_variant(int M);
-bool col_translation_supported(int M);  // translated gaps (needs the mirrored H form)
 hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
                       hipStream_t s);
 // fills out[w][|kx|][|ky|] (w < W, |kx|, |ky| <= M/2) with H / M^2 of the gap z = zrev M dx,

@@ -329,8 +329,6 @@ const char* const kColVariantNames[kColVariants] = {"tile8", "tile16", "tile8+mi
 // built-in choice when no variant is forced and no autotuning is asked for
 int default_col_variant(int M) { return !wave_local(M) ? 0 : M >= 512 ? 2 : 3; }
 
-bool col_translation_supported(int M) { return wave_local(M); }
-
 bool col_variant_supported(int M, int pad, int variant) {
   if (variant < 0 || variant >= kColVariants) return false;
   if (variant == 4) return M <= 512 && M % 16 == 0 && (M / pad) % 16 == 0;

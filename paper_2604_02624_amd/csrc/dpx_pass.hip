@@ -90,12 +90,12 @@ template <int PAD, int TX>
 hipError_t col_launch_h(int hm, bool conj, const ColArgs& a, int w_count, hipStream_t s) {
   if (hm == kHTable) return col_launch<PAD, TX, kHTable>(conj, a, w_count, s);
   if (hm == kHBand) return col_launch<PAD, TX, kHBand>(conj, a, w_count, s);
+  if (hm == kHShift) return col_launch<PAD, TX, kHShift>(conj, a, w_count, s);
   if constexpr (Geo<M>::WAVE_LOCAL) {
     if (hm == kHMirror) return col_launch<PAD, TX, kHMirror>(conj, a, w_count, s);
-    if (hm == kHShift) return col_launch<PAD, TX, kHShift>(conj, a, w_count, s);
   } else {
-    // the mirrored forms exchange H across the lanes of one wavefront
-    if (hm == kHMirror || hm == kHShift) return hipErrorInvalidValue;
+    // the mirrored form exchanges H across the lanes of one wavefront
+    if (hm == kHMirror) return hipErrorInvalidValue;
   }
   return col_launch<PAD, TX, kHEval>(conj, a, w_count, s);
 }
@@ -103,12 +103,7 @@ hipError_t col_launch_h(int hm, bool conj, const ColArgs& a, int w_count, hipStr
 template <int PAD>
 hipError_t col_variant(int variant, bool conj, const ColArgs& args, int w_count, hipStream_t s) {
   const bool shifted = args.sx != 0.0 || args.sy != 0.0;
-  ColArgs a = args;
-  if (shifted) {
-    // ramp step between a lane's registers (rows P apart), the same for every lane
-    const double ph = -2.0 * 3.14159265358979323846 * (static_cast<double>(Geo<M>::P) * a.sy);
-    a.ystep = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
-  }
+  const ColArgs& a = args;
   const int hm = h_mode(variant, a.htab != nullptr, shifted, a.band_limited != 0);
   if (col_tile_width(M, variant) == kTileNarrow) return col_launch_h<PAD, kTileNarrow>(hm, conj, a, w_count, s);
   return col_launch_h<PAD, kTileWide>(hm, conj, a, w_count, s);

@@ -266,6 +266,15 @@ __global__ void __launch_bounds__((row_block_threads<M, MODE>())) row_group_kern
   row_body<M, PAD, MODE>(a, local % t.gx, local / t.gx, lds_all, tw);
 }
 
+// The lane's first row index, opaque to the optimiser: the per-element row terms of the
+// transfer function (ky, ky^2, their conversions to FP64) are the same for every wavelength, and
+// left visible the compiler keeps all E of them live across the wavelength loop, which spills.
+// Derived from this value they are recomputed per wavelength (a few integer operations).
+__device__ __forceinline__ int opaque_lane_row(int j0) {
+  asm volatile("" : "+v"(j0));
+  return j0;
+}
+
 // H(kx, ky) / M^2 with the conjugate for the adjoint; 0 outside the propagating disc
 template <int M, bool CONJ>
 __device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
@@ -283,9 +292,8 @@ __device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
 // ------------------------------------------------------------------------------------------
 // Where a column pass takes the transfer function from: evaluated for every element, evaluated
 // for the rows ky <= M/2 and shared with the mirrored rows across lanes, or read from the
-// plan's table; a translated gap shares the symmetric part like the mirror form and multiplies
-// every element by its own translation ramp; the band-limited spectrum evaluates every element
-// inside the band.
+// plan's table; a translated gap evaluates every element with its translation ramp folded into
+// the phase; the band-limited spectrum evaluates every element inside the band.
 constexpr int kHEval = 0, kHMirror = 1, kHTable = 2, kHShift = 3, kHBand = 4;
 
 // Block (bx, by) of a column pass: column tile bx of gx, wavelength block by.  The blocks of
@@ -323,7 +331,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
   // hidden; without it those registers would not fit next to the full-length transform and
   // the rows go straight to LDS.  Row k of a lane is one buffer load at the lane's 32-bit
   // byte offset plus the scalar offset k P M 8, so no per-row address stays live.
-  constexpr bool PREFETCH = HALF && HM != kHShift && HM != kHBand;
+  constexpr bool PREFETCH = HALF && HM != kHBand;
   const int wb = by * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
   const unsigned voff = static_cast<unsigned>((((FULL ? 0 : a.in_lo) + yy) * M + kx0 + cc) * 8);
@@ -393,16 +401,18 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
     const double base = c.q0 - static_cast<double>(kxs * kxs);
     auto H = [&](int ky) { return transfer<M, CONJ>(a.zrev, base, ky); };
     if constexpr (HM == kHEval) {
+      const int jv = opaque_lane_row(j0);
 #pragma unroll
-      for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], H(j0 + P * t));
+      for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], H(jv + P * t));
     } else if constexpr (HM == kHBand) {
       // band-limited angular spectrum: H = 0 where |kx| or |ky| exceeds the band limit
       // sqrt(q0 / (4 zrev^2 + 1)) (in frequency indices), beyond which the sampled phase aliases
       const double lim = c.q0 / (4.0 * a.zrev * a.zrev + 1.0);
       const bool col_in = static_cast<double>(kxs * kxs) <= lim;
+      const int jv = opaque_lane_row(j0);
 #pragma unroll
       for (int t = 0; t < E; ++t) {
-        const int ky = j0 + P * t;
+        const int ky = jv + P * t;
         const int kys = ky < M / 2 ? ky : ky - M;
         const bool in = col_in && static_cast<double>(kys * kys) <= lim;
         reg[t] = in ? cmul(reg[t], H(ky)) : make_float2(0.f, 0.f);
@@ -419,53 +429,41 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
       }
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], CONJ ? conjf2(hv[t]) : hv[t]);
-    } else if constexpr (HM == kHMirror || HM == kHShift) {
+    } else if constexpr (HM == kHShift) {
+      // translated gap: H times the ramp exp(-i 2 pi (kx sx + ky sy)) (signed indices) is one
+      // phase per element, z sqrt(q) - kx sx - ky sy in revolutions, reduced in FP64 like H's
+      // own; conjugated for the adjoint.  Per element, so no lane holds ramp state and the
+      // next wavelength's rows still fit in registers.
+      const double px = static_cast<double>(kxs) * a.sx;
+      const int jv = opaque_lane_row(j0);
+#pragma unroll
+      for (int t = 0; t < E; ++t) {
+        const int ky = jv + P * t;
+        const int kys = ky < M / 2 ? ky : ky - M;
+        const double q = base - static_cast<double>(kys * kys);
+        const double ph = a.zrev * sqrt_pos(q > 0.0 ? q : 1.0) - fma(static_cast<double>(kys), a.sy, px);
+        const float2 hh = cis_turns<M * M>(ph);
+        reg[t] = q > 0.0 ? cmul(reg[t], CONJ ? conjf2(hh) : hh) : make_float2(0.f, 0.f);
+      }
+    } else if constexpr (HM == kHMirror) {
       // H depends on ky^2 only: lane j0 holds ky = j0 + P t, and for t >= E/2 the row M - ky
       // is register E-1-t of lane P - j0 (lane 0 mirrors onto its own register E - t), so
       // each lane evaluates E/2 + 1 rows and fetches the others across lanes.  Streamed so
       // that only two evaluations are live at a time: step u applies row u and the mirrored
       // row E-1-u (whose value lane 0 takes from its own evaluation u+1).
-      //
-      //
-      // A translated gap (kHShift) also multiplies element (kx, ky) by the ramp
-      // exp(-i 2 pi (kx sx + ky sy)) with signed indices: register u holds ky = j0 + P u and
-      // register E-1-u holds ky - M = j0 - P (u + 1), so with A = ramp(kx, j0) and
-      // B = exp(-i 2 pi P sy) their ramps are A B^u and A conj(B)^(u+1), stepped by one complex
-      // product each (A from an FP64 phase; B, the same for every lane, from the launch
-      // arguments; conjugated for the adjoint).
       constexpr int EH = E / 2;
       const int lane = threadIdx.x & 63;
       const int src = ((lane - j0) + ((P - j0) & (P - 1))) << 2;
-      float2 ra{}, rb{}, step{};
-      if constexpr (HM == kHShift) {
-        ra = cis_turns<1>(-(static_cast<double>(kxs) * a.sx + static_cast<double>(j0) * a.sy));
-        step = a.ystep;
-        if constexpr (CONJ) {
-          ra = conjf2(ra);
-          step = conjf2(step);
-        }
-        rb = cmul(ra, conjf2(step));
-      }
       float2 cur = H(j0);
 #pragma unroll
       for (int u = 0; u < EH; ++u) {
         const float2 nxt = H(j0 + P * (u + 1));
-        if constexpr (HM == kHShift) {
-          reg[u] = cmul(reg[u], cmul(cur, ra));
-          ra = cmul(ra, step);
-        } else {
-          reg[u] = cmul(reg[u], cur);
-        }
+        reg[u] = cmul(reg[u], cur);
         float2 m;
         m.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.x)));
         m.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(cur.y)));
         if (j0 == 0) m = nxt;
-        if constexpr (HM == kHShift) {
-          reg[E - 1 - u] = cmul(reg[E - 1 - u], cmul(m, rb));
-          rb = cmul(rb, conjf2(step));
-        } else {
-          reg[E - 1 - u] = cmul(reg[E - 1 - u], m);
-        }
+        reg[E - 1 - u] = cmul(reg[E - 1 - u], m);
         cur = nxt;
       }
     }

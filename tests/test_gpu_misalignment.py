@@ -182,6 +182,37 @@ def test_axial_jitter_on_matrix_core_variant_matches_oracle(torch_dev):
     assert rel_l2(I.reshape(I_ref.shape), I_ref) <= INT_TOL
 
 
+def test_translated_gaps_at_transform_1600(torch_dev):
+    say("translated and lengthened gaps at transform 1600 (800x800, input aperture and gap): "
+        "variants 0 and 1 vs the oracle")
+    d0, h, tau, u_in = wk.paper_geometry(n_wl=2, layers=2)
+    d = misaligned(d0, seed=16)
+    from paper_2604_02624_amd import dpx
+    outs = []
+    for v in (0, 1):
+        plan = dpx.Plan([d], force_variant=v)
+        hh = plan.pack_heights([h])
+        u = torch_dev.view_as_real(torch_dev.as_tensor(u_in)).reshape(-1).cuda()
+        I = plan.forward(hh, u)
+        _, g = plan.loss(I, plan.pack_images([tau]))
+        dh = plan.backward(hh, u, g)
+        torch_dev.cuda.synchronize()
+        outs.append((I.cpu().numpy(), g.cpu().numpy(), dh.cpu().numpy()))
+        plan.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    I, g, dh = outs[0]
+    I_ref = o.forward(d, h, u_in, "fft")
+    errs = [rel_l2(I.reshape(I_ref.shape)[i], I_ref[i]) for i in range(2)]
+    say(f"per-wavelength rel L2 {max(errs):.2e}")
+    assert max(errs) <= INT_TOL
+    assert rel_l2(o.forward(d0, h, u_in, "fft"), I_ref) > 100 * INT_TOL
+    dh_ref = o.grad(d, h, u_in, g.reshape(tau.shape).astype(np.float64), "fft")
+    e = rel_l2(dh.reshape(dh_ref.shape), dh_ref)
+    say(f"gradient vs oracle adjoint {e:.2e}")
+    assert e <= 1e-4
+
+
 def test_misaligned_large_workload_sampled(torch_dev):
     say("large workload (4 layers 512x512, transform 1024, 4096 wavelengths) misaligned as in the "
         "benchmark: sampled wavelengths vs the oracle")
