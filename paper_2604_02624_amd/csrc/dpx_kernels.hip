@@ -326,8 +326,10 @@ bool wave_local(int M) {
 const char* const kColVariantNames[kColVariants] = {"tile8", "tile16", "tile8+mirror",
                                                     "tile16+mirror", "dft-gemm-mfma"};
 
-// built-in choice when no variant is forced and no autotuning is asked for
-int default_col_variant(int M) { return !wave_local(M) ? 0 : M >= 512 ? 2 : 3; }
+// built-in choice when no variant is forced and no autotuning is asked for: the mirrored forms
+// where transforms stay in one wavefront; at 1600 the wide tile (8 columns, 10 waves per CU in
+// one block) beats the narrow one, which the registers hold to one 5-wave block per CU
+int default_col_variant(int M) { return !wave_local(M) ? 1 : M >= 512 ? 2 : 3; }
 
 bool col_variant_supported(int M, int pad, int variant) {
   if (variant < 0 || variant >= kColVariants) return false;

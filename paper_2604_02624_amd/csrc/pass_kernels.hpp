@@ -31,6 +31,7 @@ __device__ __forceinline__ float2 buffer_load_c64(__amdgpu_buffer_rsrc_t r, unsi
 
 // Eq. 1 with the +j reading: t = exp(-ca h) exp(+i 2 pi rt h); phase argument in double.
 __device__ __forceinline__ float2 transmission(float h, const WlConst& c) {
+  asm volatile("" : "+v"(h));  // the FP64 height stays per wavelength (as in opaque_lane_row)
   const double hd = static_cast<double>(h);
   float2 t = cis_turns(c.rt * hd);
   if (c.ca != 0.0) {
