@@ -24,6 +24,12 @@ unsigned group_grid(const GroupArgs& g) { return static_cast<unsigned>(g.block0[
 
 template <int PAD>
 hipError_t row_mode(int mode, const RowArgs& a, dim3 grid, hipStream_t s) {
+  if constexpr (M == 1600 && PAD == 2) {
+    if (mode == ROW_FWD_MID) {
+      row_kernel_w3<M, PAD, ROW_FWD_MID><<<grid, row_block_threads<M, ROW_FWD_MID>(), 0, s>>>(a);
+      return hipGetLastError();
+    }
+  }
   switch (mode) {
 #define DPX_ROW(MD) \
   case MD: row_kernel<M, PAD, MD><<<grid, row_block_threads<M, MD>(), 0, s>>>(a); break;

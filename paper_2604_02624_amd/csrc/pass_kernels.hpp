@@ -249,6 +249,17 @@ __global__ void __launch_bounds__((row_block_threads<M, MODE>())) row_kernel(Row
   row_body<M, PAD, MODE>(a, blockIdx.x, blockIdx.y, lds_all, tw);
 }
 
+// The same pass with at least three wavefronts per SIMD (a cap of 168 registers): the forward
+// middle pass at transform 1600 fits it without spilling, and three of its 240-thread blocks
+// then share a CU instead of two.
+template <int M, int PAD, int MODE>
+__global__ void __launch_bounds__((row_block_threads<M, MODE>())) __attribute__((amdgpu_waves_per_eu(3)))
+row_kernel_w3(RowArgs a) {
+  __shared__ float2 lds_all[row_block_threads<M, MODE>() / Geo<M>::P * Geo<M>::ROW_REGION];
+  __shared__ float2 tw[twiddle_count<M>()];
+  row_body<M, PAD, MODE>(a, blockIdx.x, blockIdx.y, lds_all, tw);
+}
+
 // One launch of a row pass for several designs of the same transform length and mode: each
 // block finds its design's task, patches the per-call buffers into the design's arguments
 // and runs the same body as the single-design kernel.
