@@ -314,7 +314,7 @@ def main():
                                                     40e-9, 200e-9)
             try:
                 plan.set_misalignment(0, *robustness.gap_offsets(lat, ax))
-            except dpx.DpxError as e:   # transform lengths without translated gaps
+            except dpx.DpxError as e:   # paths that cannot translate (band-limited spectrum)
                 log(f"[bench] no misaligned step: {e}")
             else:
                 step()
