@@ -340,9 +340,10 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
 
   // The block runs a.col_wpb wavelengths.  With zero padding the staged rows of the next one
   // are loaded into registers while the current one is transformed, so their latency is
-  // hidden; without it those registers would not fit next to the full-length transform and
-  // the rows go straight to LDS.  Row k of a lane is one buffer load at the lane's 32-bit
-  // byte offset plus the scalar offset k P M 8, so no per-row address stays live.
+  // hidden; without it those registers would not fit next to the full-length transform (nor
+  // next to the band-limited source's per-element band tests) and the rows go straight to LDS.
+  // Row k of a lane is one buffer load at the lane's 32-bit byte offset plus the scalar offset
+  // k P M 8, so no per-row address stays live.
   constexpr bool PREFETCH = HALF && HM != kHBand;
   const int wb = by * a.col_wpb;
   const int we = min(wb + a.col_wpb, a.w_count);
