@@ -202,7 +202,7 @@ void dpx_opts_default(dpx_opts* opts);
  * tables and twiddle tables, and allocates every device buffer the calls need on the
  * current HIP device.  designs: [n_designs] host array; opts may be NULL (defaults).
  * On success *out owns the plan.  Errors: DPX_E_ARG (shape rules above, option ranges),
- * DPX_E_UNSUPPORTED (pad*N not one of 64, 96, 128, 192, 256, 384, 512, 1024; a forced column
+ * DPX_E_UNSUPPORTED (pad*N not one of 64, 96, 128, 192, 256, 384, 512, 1024, 1600; a forced column
  * variant not built for a design; schedule 2 where it cannot run), DPX_E_NOMEM,
  * DPX_E_DEVICE. */
 dpx_status dpx_plan_create(const dpx_design* designs, int32_t n_designs, const dpx_opts* opts,
@@ -228,7 +228,7 @@ dpx_status dpx_plan_layout(const dpx_plan* plan, int32_t design, dpx_layout* out
  *   n_wl       must equal the design's wavelength count at creation
  * Layer heights, gaps, grid, field of view and workspace are unchanged.  Blocks the host until
  * the device is idle (queued passes read the old table), then uploads the table and rebuilds
- * any transfer tables.  Errors: DPX_E_ARG for a bad index, a different count or a value that
+ * any transfer tables.  A store-mode dpx_backward must follow a new dpx_forward.  Errors: DPX_E_ARG for a bad index, a different count or a value that
  * dpx_plan_create would reject (the plan is then unchanged); DPX_E_DEVICE for a failed copy. */
 dpx_status dpx_plan_set_wavelengths(dpx_plan* plan, int32_t design, const double* wl,
                                     const double* n_mat, const double* kappa, int32_t n_wl);
@@ -244,7 +244,8 @@ dpx_status dpx_plan_set_wavelengths(dpx_plan* plan, int32_t design, const double
  *   n_gaps                must equal the design's layer count
  * Takes effect for calls issued after it returns (the values travel as kernel arguments); a
  * plan with use_graph drops its captured graphs, after waiting for the device.  Forward and
- * backward must see the same misalignment.  Errors: DPX_E_ARG for a bad index or count, a
+ * backward must see the same misalignment: a store-mode dpx_backward must follow a new
+ * dpx_forward (else DPX_E_STATE).  Errors: DPX_E_ARG for a bad index or count, a
  * non-finite value or a negative gap; DPX_E_UNSUPPORTED for a non-zero misalignment on a design
  * that runs the grouped schedule, the LDS-resident path or transfer tables, or a lateral one
  * with the matrix-core column variant or the band-limited spectrum.  On error the plan is
@@ -285,7 +286,10 @@ dpx_status dpx_loss(dpx_plan* plan, const float* intensity, const float* target,
  *   dl_dh [sum K N N] (device, written; summed over wavelengths in a fixed order, so the
  *   result is bitwise reproducible).
  * Store mode: needs the most recent dpx_forward on this plan with the same h and u_in
- * pointers (and unchanged contents), else DPX_E_STATE.  Recompute mode: no precondition. */
+ * pointers, with no dpx_plan_set_wavelengths or dpx_plan_set_misalignment in between, else
+ * DPX_E_STATE.  The contents of h and u_in must not change between that forward and this call
+ * (the library cannot see a write through the pointers, e.g. by dpx_adam_step: run the
+ * forward again after it).  Recompute mode: no precondition. */
 dpx_status dpx_backward(dpx_plan* plan, const float* h, const float* u_in, const float* dl_di,
                         float* dl_dh, void* stream);
 
@@ -326,7 +330,12 @@ typedef enum dpx_pass {
                                  from u_in and h instead of read back) */
   DPX_PASS_LDS_FWD = 8,       /* LDS-resident forward of a whole design (short transforms) */
   DPX_PASS_LDS_ADJ = 9,       /* LDS-resident adjoint of a whole design */
-  DPX_PASS_COUNT = 10
+  /* the column launches that read and keep every aperture row (one kernel instance each: all
+   * but the last forward and the first adjoint column pass), counted a second time here; they
+   * are a subset of DPX_PASS_COL_FWD / DPX_PASS_COL_ADJ */
+  DPX_PASS_COL_FWD_FULL = 10,
+  DPX_PASS_COL_ADJ_FULL = 11,
+  DPX_PASS_COUNT = 12
 } dpx_pass;
 
 /* Per-pass timers (measurement support).  While enabled, every launch of the passes above is

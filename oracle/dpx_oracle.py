@@ -311,6 +311,30 @@ def forward(design: dict, h: np.ndarray, u_in=None, mode: str = "naive", keep: b
     return out
 
 
+def forward_phase_only(design: dict, phi: np.ndarray, lam_ref: float, u_in=None, mode: str = "naive",
+                       wavelengths=None):
+    """Intensity images of a cascade of phase-only layers (Eq. 3, the spatial light modulators of
+    the experiment): layer l multiplies the field by phase_only_transmission(phi[l]) at each
+    wavelength, then the gap of Eq. 4/5 follows exactly as in ``forward`` (same padding, cut,
+    crop and field of view).  phi [K, N, N] radians at lam_ref.  No input gap, no misalignment."""
+    N, K = design["n"], design["layers"]
+    ws = range(design["n_wl"]) if wavelengths is None else list(wavelengths)
+    fs = fov_slice(design)
+    b = design["bin"]
+    T = design["fov"] // b
+    u0 = np.ones((N, N), np.complex128) if u_in is None else np.asarray(u_in, np.complex128)
+    out = np.zeros((len(ws), T, T), dtype=np.float64)
+    for i, w in enumerate(ws):
+        wl = float(design["wl"][w])
+        u = u0
+        for l in range(K):
+            v = phase_only_transmission(phi[l], wl, lam_ref) * u
+            z, sh = gap(design, l)
+            u = propagate(v, design["pad"], design["dx"], wl, design["n_medium"], z, mode, shift=sh)
+        out[i] = bin_sum(np.abs(u[fs, fs]) ** 2, b)
+    return out
+
+
 def loss(I: np.ndarray, tau: np.ndarray):
     """L = (1/W) sum_w mean_p (I_w,p / S_w - tau_w,p / sum tau_w)^2 and dL/dI.
 

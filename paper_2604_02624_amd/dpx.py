@@ -352,7 +352,8 @@ class Plan:
 
     # -------------------------------------------------------------- per-pass timers
     PASS_NAMES = ["col_fwd", "col_adj", "row_fwd_first", "row_fwd_mid", "row_fwd_last",
-                  "row_adj_seed", "row_adj_mid", "row_adj_last", "lds_fwd", "lds_adj"]
+                  "row_adj_seed", "row_adj_mid", "row_adj_last", "lds_fwd", "lds_adj",
+                  "col_fwd_full", "col_adj_full"]
 
     def timing(self, enable: bool = True):
         _check(self.lib, self.lib.dpx_timing_enable(self._h, 1 if enable else 0))

@@ -165,3 +165,39 @@ def test_quantised_training_matches_oracle_loop(torch_dev):
     ps16, ps4 = tr.evaluate(bits=16), tr.evaluate(bits=4)
     assert np.isfinite(ps16).all() and np.isfinite(ps4).all()
     tr.close()
+
+
+@pytest.mark.parametrize("n,K,W", [(64, 2, 6), (512, 4, 3)])
+def test_phase_only_layers_match_the_eq3_cascade(torch_dev, n, K, W):
+    """Phase-only layers (Eq. 3) run on the thickness kernels through layer_models; the oracle
+    multiplies by the Eq. 3 transmission directly (its own cascade).  Transforms 128 and 1024."""
+    say(f"phase-only layers: N={n} (transform {2 * n}), {K} layers, {W} wavelengths vs the Eq. 3 cascade")
+    from paper_2604_02624_amd import dpx, layer_models as lm
+    g = np.random.default_rng(n + K)
+    wl = np.linspace(450e-9, 750e-9, W)
+    lam_ref = 600e-9
+    F = min(n, 64)
+    base = wk.make_design(n=n, layers=K, wl=wl, n_mat=wk.cauchy_index(wl), dx=0.3e-6, z=30e-6, fov=F)
+    d = lm.phase_only_design(base)
+    phi = g.uniform(0.0, 2 * np.pi, (K, n, n))
+    h = lm.heights_from_phase(phi, lam_ref)
+    phi_h = lm.phase_from_heights(h, lam_ref)          # the phases the float32 heights carry
+    I_ref = o.forward_phase_only(d, phi_h, lam_ref, None, "fft")
+    plan = dpx.Plan([d])
+    ht = plan.pack_heights([h])
+    I = plan.forward(ht).cpu().numpy().reshape(I_ref.shape)
+    errs = [rel_l2(I[i], I_ref[i]) for i in range(W)]
+    say(f"rel L2 {np.max(errs):.2e}")
+    assert max(errs) <= INT_TOL
+    if n == 64:
+        # dL/dphi = dL/dh lambda_ref / (2 pi): the thickness adjoint against the oracle's
+        tau = g.uniform(0.0, 1.0, (W, F, F)).astype(np.float32)
+        I_t = torch_dev.as_tensor(I.reshape(-1)).cuda()
+        _, gi = plan.loss(I_t, plan.pack_images([tau]))
+        dh = plan.backward(ht, None, gi).cpu().numpy().reshape(K, n, n)
+        _, g_ref, _ = o.loss(I_ref, tau)
+        dh_ref = o.grad(d, h, None, g_ref.astype(np.float32), "fft")
+        err = rel_l2(dh, dh_ref)
+        say(f"gradient rel {err:.2e}")
+        assert err <= 1e-4
+    plan.close()

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import dpx_oracle as o
+from tests import oracle_threads as ot
 from paper_2604_02624_amd import workloads as wk
 
 pytestmark = pytest.mark.gpu
@@ -232,28 +233,123 @@ def test_batched_five_layers_256(torch_dev):
     assert err <= 1e-4
 
 
-def test_large_full_size_sampled(torch_dev):
-    say("large: 4 layers 512x512 pad 1024, 4096 wavelengths (oracle on 3 sampled wavelengths)")
+def large_sample(W=4096, wpb_row=16, wpb_col=2):
+    """Eight seeded wavelengths of the large workload (stream 3): the first and last wavelength
+    of one row-pass block of 16, both wavelengths of one column-pass block of 2, the two ends of
+    the band and two more drawn at random, in index order."""
+    g = np.random.default_rng(np.random.SeedSequence([260402624, 4, 3]))
+    b = int(g.integers(1, W // wpb_row - 1))
+    c = int(g.integers(0, W // wpb_col))
+    picks = {0, W - 1, b * wpb_row, b * wpb_row + wpb_row - 1, wpb_col * c, wpb_col * c + 1}
+    while len(picks) < 8:
+        picks.add(int(g.integers(0, W)))
+    return sorted(picks), g
+
+
+@pytest.fixture(scope="module")
+def large_run(torch_dev):
+    """The large workload on the GPU in the benchmark's launch configuration (all 4096
+    wavelengths, one plan, store mode), with the adjoint seeded by the oracle's dL/dI of the loss
+    over the sampled wavelengths, so dL/dh is the gradient of that loss alone."""
+    say("large: 4 layers 512x512 pad 1024, 4096 wavelengths (oracle on 8 seeded wavelengths)")
     w = wk.make_workload(4)
     d, h, tau = w["designs"][0], w["h"][0], w["targets"][0]
-    sample = [0, 2047, 4095]
-    I_ref = o.forward(d, h, None, "fft", wavelengths=sample)
+    sample, g = large_sample()
+    say(f"sampled wavelengths {sample}")
+    I_ref = ot.forward(d, h, None, sample)
     _, g_s, _ = o.loss(I_ref, tau[sample])
     dl_di = np.zeros((4096, 64, 64), np.float32)
     dl_di[sample] = g_s
     r = run_gpu(torch_dev, [d], [h], [tau], dl_di=[dl_di])
-    I_gpu = r["I"].cpu().numpy().reshape(4096, 64, 64)
-    errs = per_wl_rel(I_gpu[sample], I_ref)
+    out = dict(d=d, h=h, tau=tau, sample=sample, rng=g, I_ref=I_ref, g_s=g_s,
+               I=r["I"].cpu().numpy().reshape(4096, 64, 64),
+               dh=r["dh"].cpu().numpy().reshape(h.shape).astype(np.float64))
+    r["plan"].close()
+    del r
+    torch_dev.cuda.empty_cache()
+    return out
+
+
+def test_large_full_size_sampled(large_run):
+    r = large_run
+    sample = r["sample"]
+    errs = per_wl_rel(r["I"][sample], r["I_ref"])
     say(f"rel L2 {errs}")
     assert errs.max() <= INT_TOL
-    assert np.isfinite(I_gpu).all()
-    dh_ref = o.grad(d, h, None, g_s.astype(np.float32), "fft", wavelengths=sample)
-    err = rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref)
-    say(f"gradient rel {err:.3e}")
+    assert np.isfinite(r["I"]).all()
+    dh_ref = ot.grad(r["d"], r["h"], None, r["g_s"].astype(np.float32), sample)
+    err = rel_l2(r["dh"], dh_ref)
+    say(f"gradient rel {err:.3e} (oracle adjoint)")
     assert err <= 1e-4
     # property at full size: each layer's gradient sums to ~0 (global-phase invariance)
-    dh = r["dh"].cpu().numpy().reshape(h.shape).astype(np.float64)
+    dh = r["dh"]
     assert (np.abs(dh.sum(axis=(1, 2))) <= 1e-3 * np.abs(dh).sum(axis=(1, 2))).all()
+
+
+def test_large_gradient_vs_finite_differences_directions(large_run):
+    """Central differences of the FP64 oracle's loss over the sampled wavelengths along 8 seeded
+    random directions (stream 4), step 1e-3 lambda_m: |<g, v> - FD_v| / |FD_v| <= 1e-3."""
+    r = large_run
+    d, h, sample = r["d"], r["h"], r["sample"]
+    tau_s = r["tau"][sample]
+    lam_m = 600e-9
+    delta = 1e-3 * lam_m
+    gv = np.random.default_rng(np.random.SeedSequence([260402624, 4, 4]))
+    h64 = h.astype(np.float64)
+    errs = []
+    for k in range(8):
+        v = gv.standard_normal(h.shape)
+        fd = (ot.loss(d, h64 + delta * v, None, tau_s, sample)
+              - ot.loss(d, h64 - delta * v, None, tau_s, sample)) / (2 * delta)
+        errs.append(abs(float((r["dh"] * v).sum()) - fd) / abs(fd))
+        say(f"direction {k}: rel {errs[-1]:.2e}")
+    assert max(errs) <= GRAD_TOL
+
+
+def test_large_gradient_vs_finite_differences_pixels(large_run):
+    """Central differences of the FP64 oracle's loss over the sampled wavelengths at 64 seeded
+    pixels of the last layer (stream 3), step 1e-3 lambda_m: relative L2 over the pixels
+    <= 1e-3.  A height of the last layer only changes the last propagation, so each loss is
+    evaluated from the field arriving at that layer (the oracle's own forward of the first
+    layers, kept once) through the oracle's one-layer forward: the same operations as a full
+    forward, without recomputing the unchanged layers."""
+    r = large_run
+    d, h, sample, g = r["d"], r["h"], r["sample"], r["rng"]
+    K, N = d["layers"], d["n"]
+    tau_s = r["tau"][sample]
+    lam_m = 600e-9
+    delta = 1e-3 * lam_m
+    h64 = h.astype(np.float64)
+    # the field arriving at the last layer, per sampled wavelength
+    def arriving(w):
+        _, vs, _ = o.forward(d, h, None, "fft", keep=True, wavelengths=[w])
+        t = o.transmission(h64[K - 1], float(d["wl"][w]), float(d["n_mat"][w]), 0.0, d["n_medium"])
+        return vs[0, K - 1] / t
+    u_arr = dict(zip(sample, ot._map(arriving, sample)))
+    last = dict(d, layers=1, z=np.asarray(d["z"])[K - 1:K])
+
+    def loss_last(hl):
+        I = np.concatenate([o.forward(last, hl[None], u_arr[w], "fft", wavelengths=[w]) for w in sample])
+        return o.loss(I, tau_s)[0]
+
+    # the suffix evaluation reproduces the full forward's loss
+    full = o.loss(r["I_ref"], tau_s)[0]
+    assert abs(loss_last(h64[K - 1]) - full) <= 1e-12 * abs(full)
+    pix = [(int(g.integers(0, N)), int(g.integers(0, N))) for _ in range(64)]
+
+    def fd(p):
+        y, x = p
+        hp = h64[K - 1].copy()
+        hm = h64[K - 1].copy()
+        hp[y, x] += delta
+        hm[y, x] -= delta
+        return (loss_last(hp) - loss_last(hm)) / (2 * delta)
+
+    fds = np.array(ot._map(fd, pix))
+    gpu = np.array([r["dh"][K - 1, y, x] for y, x in pix])
+    err = float(np.linalg.norm(gpu - fds) / np.linalg.norm(fds))
+    say(f"64 pixels of layer {K - 1}: rel L2 {err:.2e}")
+    assert err <= GRAD_TOL
 
 
 def test_uneven_designs_in_one_plan(torch_dev):
@@ -540,6 +636,18 @@ def test_error_paths(torch_dev):
     with pytest.raises(dpx.DpxError) as e:
         plan.backward(h.clone(), None, g)
     assert e.value.status == dpx.DPX_E_STATE
+    plan.backward(h, None, g)
+    # rebinding the wavelengths or setting a misalignment leaves the stored fields stale
+    d0 = w["designs"][0]
+    for change in (lambda: plan.set_wavelengths(0, d0["wl"], d0["n_mat"]),
+                   lambda: plan.set_misalignment(0, dz=np.full(d0["layers"], 1e-8)),
+                   lambda: plan.set_misalignment(0)):
+        plan.forward(h)
+        change()
+        with pytest.raises(dpx.DpxError) as e:
+            plan.backward(h, None, g)
+        assert e.value.status == dpx.DPX_E_STATE
+    plan.forward(h)
     plan.backward(h, None, g)
     with pytest.raises(ValueError):
         plan.forward(h[:-1].contiguous())

@@ -122,3 +122,49 @@ def test_phase_only_layer_is_the_unit_contrast_thickness_model():
     for wl in (0.45e-6, 0.6e-6, 0.74e-6):
         t = o.transmission(phi * lam_ref / (2 * np.pi), wl, 1.0 + 1.0, 0.0, 1.0)
         assert rel(o.phase_only_transmission(phi, wl, lam_ref), t) < 1e-13
+
+
+@pytest.mark.parametrize("wl", [0.6e-6, 0.47e-6])
+def test_phase_only_grating_diffraction_orders(wl):
+    """Closed form for a cascade of Eq. 3 layers: a sinusoidal phase grating
+    phi(x) = a cos(2 pi p x / N) at lambda_ref transmits exp(j a' cos theta), a' = a lambda_ref /
+    lambda, which by the Jacobi-Anger expansion is sum_m j^m J_m(a') exp(j m theta); on a periodic
+    grid of N samples (pad 1) order m is the grid frequency s = m p mod N (signed), which
+    propagates with kz = sqrt(k^2 - (2 pi s / (N dx))^2) and is cut when that is imaginary.  The
+    window intensity follows sample by sample."""
+    from scipy.special import jv
+    N, F, p, a, lam_ref, z = 32, 16, 3, 1.7, 0.6e-6, 5.3e-6
+    dx = 0.3e-6
+    d = wk.make_design(n=N, layers=1, wl=np.array([wl]), n_mat=2.0, dx=dx, z=[z], fov=F, pad=1)
+    x = np.arange(N)
+    phi = np.broadcast_to(a * np.cos(2 * np.pi * p * x / N), (N, N))[None]
+    I = o.forward_phase_only(d, phi, lam_ref, None, "fft")[0]
+    k = 2 * np.pi / wl
+    ap = a * lam_ref / wl
+    xs = np.arange((N - F) // 2, (N + F) // 2)
+    field = np.zeros(F, complex)
+    for m in range(-40, 41):           # |J_m(a')| < 1e-30 beyond
+        sf = (m * p) % N
+        sf = sf - N if sf >= N // 2 else sf
+        kx = 2 * np.pi * sf / (N * dx)
+        if kx * kx >= k * k:
+            continue
+        kz = np.sqrt(k * k - kx * kx)
+        field += (1j ** m) * jv(m, ap) * np.exp(1j * (2 * np.pi * sf * xs / N + kz * z))
+    ref = np.broadcast_to(np.abs(field) ** 2, (F, F))
+    assert rel(I, ref) < 1e-12
+
+
+def test_phase_only_cascade_is_the_unit_contrast_thickness_cascade():
+    """Eq. 3 layers are the thickness model with n - n_m = 1, no absorption and
+    h = phi lambda_ref / (2 pi) (an identity of the two transmissions), so the two cascades agree
+    wherever the heights carry the phases exactly."""
+    g = np.random.default_rng(5)
+    wl = np.array([0.45e-6, 0.6e-6, 0.74e-6])
+    lam_ref = 0.6e-6
+    d = wk.make_design(n=16, layers=3, wl=wl, n_mat=2.0, dx=0.25e-6, z=[4e-6, 3e-6, 5e-6], fov=8)
+    h = g.uniform(0, 1.2e-6, (3, 16, 16)).astype(np.float32)
+    phi = h.astype(np.float64) * (2 * np.pi / lam_ref)
+    I_p = o.forward_phase_only(d, phi, lam_ref, None, "naive")
+    I_t = o.forward(d, h, None, "naive")
+    assert rel(I_p, I_t) < 1e-12

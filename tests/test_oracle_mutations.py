@@ -103,12 +103,39 @@ def _phase_only_sign_flipped(phi, wl, lam_ref):
     return np.exp(-1j * np.asarray(phi, float) * (lam_ref / wl))
 
 
+def _phase_only_unscaled(design, phi, lam_ref, u_in=None, mode="naive", wavelengths=None):
+    """Eq. 3 layers that impose phi at every wavelength (no lambda_ref / lambda scaling)."""
+    ws = range(design["n_wl"]) if wavelengths is None else list(wavelengths)
+    out = []
+    for w in ws:
+        d1 = dict(design, wl=np.array([design["wl"][w]]), n_mat=np.array([design["n_mat"][w]]),
+                  n_wl=1, kappa=None)
+        lay = np.asarray(phi, np.float64) * (float(design["wl"][w]) / (2 * np.pi))
+        out.append(_orig_forward(dict(d1, n_mat=np.array([design["n_medium"] + 1.0])), lay, u_in, mode)[0])
+    return np.array(out)
+
+
 def _idft_no_norm(V, mode="naive"):
     return np.fft.ifft2(V, axes=(-2, -1)) * V.shape[-1]
 
 
 def _crop_shifted(U, N):
     return U[..., 1:1 + N, 1:1 + N]
+
+
+def _fov_at_corner(design):
+    return slice(0, design["fov"])
+
+
+def _fov_at_far_corner(design):
+    N, F = design["n"], design["fov"]
+    return slice(N - F, N)
+
+
+def _fov_one_sample_off(design):
+    N, F = design["n"], design["fov"]
+    a = (N - F) // 2 + 1
+    return slice(a, a + F)
 
 
 def _t_sign_flipped(h, wl, n_mat, kappa, n_medium):
@@ -173,6 +200,7 @@ CASES = [
     ("quantize_heights", _quantize_power_of_two_levels, [fpins.test_quantiser_one_bit_and_exact_levels]),
     ("band_limit", _band_limit_without_factor_two, [fpins.test_band_limit_is_where_the_sampled_phase_steps_by_pi, (64, 20e-6)]),
     ("transfer_function", _h_band_limited_x_only, [fpins.test_band_limited_transfer_function_is_a_symmetric_mask]),
+    ("forward_phase_only", _phase_only_unscaled, [fpins.test_phase_only_grating_diffraction_orders, (0.47e-6,)]),
     ("phase_only_transmission", _phase_only_sign_flipped, [fpins.test_phase_only_layer_is_the_unit_contrast_thickness_model]),
     ("forward", _forward_without_input_gap, [gpins.test_input_gap_equals_a_leading_transparent_layer]),
     ("transfer_function", _h_ramp_sign_flipped, [mpins.test_integer_shift_on_periodic_grid_is_a_roll, (3, -2)]),
@@ -186,6 +214,11 @@ CASES = [
     ("transfer_function", _h_axes_scaled, [pins.test_tilted_plane_wave, (0, 5)]),
     ("idft2", _idft_no_norm, [pins.test_normal_plane_wave_picks_up_exp_jkz]),
     ("crop_centered", _crop_shifted, [pins.test_mirror_symmetry_and_linearity]),
+    ("fov_slice", _fov_at_corner, [pins.test_field_of_view_is_the_central_window, (16, 8, 1)]),
+    ("fov_slice", _fov_at_far_corner, [pins.test_field_of_view_is_the_central_window, (18, 8, 2)]),
+    ("fov_slice", _fov_one_sample_off, [pins.test_field_of_view_is_the_central_window, (20, 12, 4)]),
+    ("fov_slice", _fov_at_corner, [pins.test_field_of_view_of_a_symmetric_design_is_flip_symmetric]),
+    ("fov_slice", _fov_at_far_corner, [pins.test_field_of_view_of_a_symmetric_design_is_flip_symmetric]),
     ("transmission", _t_sign_flipped, [pins.test_prism_deflects_toward_thicker_side]),
     ("transmission", _t_index_not_relative, [pins.test_prism_deflects_toward_thicker_side]),
     ("loss", _loss_missing_inner, [pins.test_loss_gradient_finite_difference_and_euler]),

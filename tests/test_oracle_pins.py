@@ -237,6 +237,54 @@ def test_prism_deflects_toward_thicker_side():
     assert abs(cx - z * math.tan(theta)) < 0.02 * z * math.tan(theta)
 
 
+@pytest.mark.parametrize("N,F,b", [(16, 8, 1), (18, 8, 2), (20, 12, 4)])
+def test_field_of_view_is_the_central_window(N, F, b):
+    """Placement of the F x F field of view (Section 4, the output window in the middle of the
+    output plane): on a periodic grid (pad 1) a uniform wave plus a tilted one interferes into
+    the closed form I(x, y) = 2 + 2 cos(2 pi (p x + q y) / N + kz_t z - k z), so the binned
+    image of the window starting at ((N - F) / 2, (N - F) / 2) is known sample by sample.
+    p != q, so a window displaced along either axis (or with its axes swapped) fails; the
+    sizes are chosen so that no tested displacement is a whole period of the pattern."""
+    wl, n_m, z, p, q = 0.5e-6, 1.0, 7.3e-6, 1, 2
+    dx = wl / 2
+    yy, xx = np.mgrid[0:N, 0:N]
+    u_in = 1.0 + np.exp(2j * math.pi * (p * xx + q * yy) / N)
+    d = _one_layer_design(N, [wl], 1.5, z, pad=1, fov=F, dx=dx)
+    d["bin"] = b
+    I = o.forward(d, np.zeros((1, N, N), np.float32), u_in, "fft")[0]
+    k = 2 * math.pi * n_m / wl
+    kt = 2 * math.pi / (N * dx)
+    dphi = math.sqrt(k * k - (p * kt) ** 2 - (q * kt) ** 2) * z - k * z
+    a = (N - F) // 2
+    ys, xs = np.mgrid[a:a + F, a:a + F]
+    full = 2.0 + 2.0 * np.cos(2 * math.pi * (p * xs + q * ys) / N + dphi)
+    T = F // b
+    ref = full.reshape(T, b, T, b).sum(axis=(1, 3))
+    assert I.shape == (T, T)
+    assert rel(I, ref) < 1e-12
+
+
+def test_field_of_view_of_a_symmetric_design_is_flip_symmetric():
+    """A design that is mirror symmetric about the centre of its N x N aperture (uniform input,
+    heights symmetric under x -> N-1-x and y -> N-1-y, zero padding around the aperture) has a
+    mirror-symmetric output field, and the central window maps onto itself under the same
+    mirror; so the binned image is symmetric under both flips.  A window shifted off the centre
+    (a = 0, a = N - F, or one sample off) sees a different part of the field and fails."""
+    g = np.random.default_rng(11)
+    N, F = 24, 10
+    wl = np.array([0.5e-6, 0.62e-6])
+    half = g.uniform(0, 1e-6, (2, N // 2, N // 2))
+    h = np.concatenate([half, half[:, :, ::-1]], axis=2)
+    h = np.concatenate([h, h[:, ::-1, :]], axis=1).astype(np.float32)
+    d = _one_layer_design(N, wl, 1.5, [6e-6, 4e-6], pad=2, fov=F, layers=2, dx=0.25e-6)
+    I = o.forward(d, h, None, "fft")
+    assert rel(I, I[:, ::-1, :]) < 1e-12
+    assert rel(I, I[:, :, ::-1]) < 1e-12
+    # the field is not flat over the aperture, so the symmetry is not trivial
+    full = o.forward(dict(d, fov=N), h, None, "fft")
+    assert rel(full[:, :F, :F], full[:, :F, :F][:, ::-1, ::-1]) > 1e-3
+
+
 def test_global_phase_and_two_pi_wrap_invariance():
     g = np.random.default_rng(7)
     N, K = 24, 2
