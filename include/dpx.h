@@ -293,6 +293,21 @@ dpx_status dpx_loss(dpx_plan* plan, const float* intensity, const float* target,
 dpx_status dpx_backward(dpx_plan* plan, const float* h, const float* u_in, const float* dl_di,
                         float* dl_dh, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, allocation-free
+ * serving or training loops, harnesses that forbid hipMalloc): the loss and dL/dI of dpx_loss for
+ * the images of ONE design, without a plan.  Same kernels and the same bits as dpx_loss on a plan
+ * holding that design.  The per-wavelength partial sums live in a fixed library-owned device
+ * array of DPX_STATIC_LOSS_MAX_WL doubles (512 KiB), one per GPU, held until the process ends;
+ * the call allocates nothing.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (on different streams, or from different threads) race and may return wrong values.
+ *   intensity, target [n_wl][T][T] f32 (device, read);  loss [1] double (device, written);
+ *   dl_di [n_wl][T][T] f32 (device, written) or NULL to skip;  1 <= n_wl <= DPX_STATIC_LOSS_MAX_WL.
+ * Errors: DPX_E_ARG (NULL or misaligned pointers, n_wl or T out of range; nothing is enqueued),
+ * DPX_E_DEVICE (launch failure, a pending device error). */
+#define DPX_STATIC_LOSS_MAX_WL 65536
+dpx_status dpx_loss_static(const float* intensity, const float* target, int32_t n_wl, int32_t T,
+                           double* loss, float* dl_di, void* stream);
+
 /* Per-wavelength PSNR of the intensity images against the targets (evaluation, Section 2:
  * output PSNR per image-wavelength pair), both normalised to unit sum as in the loss:
  *   psnr_w = 10 log10( max_p tau_w,p^2 / mean_p (I_w,p - tau_w,p)^2 )   (normalised images)

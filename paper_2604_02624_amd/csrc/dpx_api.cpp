@@ -1666,6 +1666,30 @@ dpx_status dpx_backward(dpx_plan* p, const float* h, const float* u_in, const fl
   return ok();
 }
 
+static_assert(DPX_STATIC_LOSS_MAX_WL == dpx::kStaticLossMaxWl, "header and library agree on the fixed array");
+
+dpx_status dpx_loss_static(const float* intensity, const float* target, int32_t n_wl, int32_t T, double* loss,
+                           float* dl_di, void* stream) {
+  DPX_TRY(check_ptr(intensity, 4, "intensity"));
+  DPX_TRY(check_ptr(target, 4, "target"));
+  DPX_TRY(check_ptr(loss, 8, "loss"));
+  if (dl_di) DPX_TRY(check_ptr(dl_di, 4, "dl_di"));
+  if (n_wl < 1 || n_wl > DPX_STATIC_LOSS_MAX_WL)
+    return fail(DPX_E_ARG, "n_wl must be in [1, %d] (got %d)", DPX_STATIC_LOSS_MAX_WL, n_wl);
+  if (T < 1 || T > 46340) return fail(DPX_E_ARG, "T must be in [1, 46340] (got %d)", T);
+  DPX_TRY(sticky_check());
+  double* part = nullptr;
+  hipError_t e = dpx::static_loss_scratch(&part);
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "fixed loss array lookup failed: %s", hipGetErrorString(e));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every partial is written by the first kernel before the second reads it, so the array
+  // needs no clearing
+  e = dpx::launch_loss(intensity, target, dl_di, part, n_wl, T, s);
+  if (e == hipSuccess) e = dpx::launch_loss_sum(part, loss, n_wl, s);
+  if (e != hipSuccess) return fail(DPX_E_DEVICE, "loss launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 dpx_status dpx_psnr(dpx_plan* p, const float* intensity, const float* target, double* psnr, void* stream) {
   if (!p) return fail(DPX_E_ARG, "plan is NULL");
   DPX_TRY(check_ptr(intensity, 4, "intensity"));

@@ -246,6 +246,10 @@ hipError_t launch_bin_intensity(const float2* ofov, float* out, int w_count, int
 hipError_t launch_loss(const float* I, const float* tau, float* dl_di, double* per_wl, int W, int T,
                        hipStream_t s);
 hipError_t launch_loss_sum(const double* per_wl, double* loss, int W, hipStream_t s);
+// most wavelengths dpx_loss_static takes (its partials live in a fixed device array)
+constexpr int kStaticLossMaxWl = 65536;
+// device address of that array on the current device (looked up once per device)
+hipError_t static_loss_scratch(double** out);
 hipError_t launch_dh_reduce(const float* part, float* dh, int nchunk, int64_t per_chunk,
                             hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);

@@ -3,6 +3,7 @@
 // the per-length pass launchers (dpx_pass.hip, one translation unit per length).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "dpx_internal.hpp"
@@ -117,6 +118,32 @@ loss_sum_group_kernel(const LossTask* __restrict__ tasks, double* __restrict__ l
   __shared__ double sh[kLossThreads];
   const LossTask& t = tasks[blockIdx.x];
   loss_sum_body(t.per_wl, loss + blockIdx.x, t.W, sh);
+}
+
+// Fixed device array for the per-wavelength loss partials of dpx_loss_static (callers that cannot
+// allocate): every GPU the library runs on holds one copy until the process ends.  Host code
+// never passes the array's name to a kernel (in host code it is a stand-in, not a device
+// address); static_loss_scratch() returns the device address, looked up once per device.
+static __device__ __align__(256) double scratch[kStaticLossMaxWl];
+
+constexpr int kMaxScratchDevices = 64;
+
+hipError_t static_loss_scratch(double** out) {
+  static std::mutex mu;
+  static void* ptr[kMaxScratchDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = p;
+  }
+  *out = static_cast<double*>(ptr[dev]);
+  return hipSuccess;
 }
 
 __device__ __forceinline__ void dh_reduce_body(const float* __restrict__ part, float* __restrict__ dh,

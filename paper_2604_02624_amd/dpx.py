@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     lib.dpx_plan_variant.restype = ctypes.c_int
     lib.dpx_plan_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     lib.dpx_plan_schedule.restype = ctypes.c_int
+    lib.dpx_loss_static.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    lib.dpx_loss_static.restype = ctypes.c_int
     lib.dpx_psnr.argtypes = [vp, vp, vp, vp, vp]
     lib.dpx_psnr.restype = ctypes.c_int
     d64 = ctypes.c_double
@@ -438,3 +440,23 @@ def quantize_heights(h, h_max, bits, out=None, stream=None):
         raise ValueError("out must be a contiguous float32 device tensor like h")
     _check(lib, lib.dpx_quantize_heights(_ptr(h), _ptr(out), h.numel(), float(h_max), int(bits), _stream(stream)))
     return out
+
+
+STATIC_LOSS_MAX_WL = 65536
+
+
+def loss_static(intensity, target, n_wl: int, T: int, loss_out=None, dl_di=None, want_grad=True, stream=None):
+    """dpx_loss_static: the loss of one design's [n_wl][T][T] images without a plan; it allocates
+    no device memory inside the library (see include/dpx.h).  Returns (loss[1], dl_di)."""
+    import torch
+    lib = load_library()
+    n = n_wl * T * T
+    Plan._check_dev(intensity, n, torch.float32, "intensity")
+    Plan._check_dev(target, n, torch.float32, "target")
+    if loss_out is None:
+        loss_out = torch.empty(1, dtype=torch.float64, device=intensity.device)
+    if want_grad and dl_di is None:
+        dl_di = torch.empty(n, dtype=torch.float32, device=intensity.device)
+    _check(lib, lib.dpx_loss_static(_ptr(intensity), _ptr(target), n_wl, T, _ptr(loss_out),
+                                    _ptr(dl_di), _stream(stream)))
+    return loss_out, dl_di
