@@ -30,6 +30,14 @@ METRIC = "wavelength·layer propagations/s (fwd+adjoint) + % HBM roofline vs pla
 UNIT = "propagations/s"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFS = 157.3
+# the issue ceiling of single FP32 operations (this build emits no packed FP32): 256 CUs x 4
+# SIMDs x 16 lanes x 2 flops (fused multiply-add) x 2.4 GHz
+FP32_NONPACKED_PEAK_TFS = 78.6
+# kernel instances the per-pass timers report one by one (a pass kind of the row passes is one
+# kernel; the column pass kinds split into the full-plane instance and the rest)
+INSTANCE_PASSES = ("col_fwd_full", "col_adj_full", "row_fwd_first", "row_fwd_mid", "row_fwd_last",
+                   "row_adj_seed", "row_adj_mid", "row_adj_last", "lds_fwd", "lds_adj")
+AGGREGATE_ONLY = ("col_fwd_full", "col_adj_full")   # subsets of col_fwd / col_adj
 WORKLOAD_NAMES = {
     1: "small forward: 2 layers 64x64 (pad 128), 6 wavelengths 500-740 nm",
     2: "small fwd+adjoint: 2 layers 64x64 (pad 128), 6 wavelengths 500-740 nm, binary targets",
@@ -106,18 +114,26 @@ def plain_loop_rate(torch, d, h, tau, n_sample, device, u_in=None):
 # ------------------------------------------------------------------------------------------
 # FP64 CPU oracle on a bounded sample of the workload
 # ------------------------------------------------------------------------------------------
-def cpu_baseline(d, h, tau, budget_s, u_in=None):
+def cpu_baseline(d, h, tau, budget_s, u_in=None, pool=None, threads=1):
+    """The oracle as it stands, one call per wavelength (forward, loss, adjoint), run on
+    `threads` host threads at once (numpy's transforms release the interpreter lock), over
+    wavelengths in a seeded random order until about budget_s seconds have passed."""
     import numpy as np
     from oracle import dpx_oracle as o
     W, K = d["n_wl"], d["layers"]
     order = np.random.default_rng(7).permutation(W)
-    done, t0 = 0, time.perf_counter()
-    while done < 2 or (time.perf_counter() - t0 < budget_s and done < W):
-        w = int(order[done])
+
+    def one(w):
+        w = int(w)
         I = o.forward(d, h, u_in, "fft", wavelengths=[w])
         _, g, _ = o.loss(I, tau[[w]])
         o.grad(d, h, u_in, g, "fft", wavelengths=[w])
-        done += 1
+
+    done, t0 = 0, time.perf_counter()
+    while done < W and (done < 2 * threads or time.perf_counter() - t0 < budget_s):
+        batch = order[done:done + threads]
+        list(pool.map(one, batch)) if pool is not None else [one(w) for w in batch]
+        done += len(batch)
     dt = time.perf_counter() - t0
     model = ""
     try:
@@ -125,10 +141,11 @@ def cpu_baseline(d, h, tau, budget_s, u_in=None):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return dict(value=done * K / dt, unit=UNIT, cores=1, kind="oracle", host_cpus=os.cpu_count(),
+    return dict(value=done * K / dt, unit=UNIT, cores=threads, kind="oracle", host_cpus=os.cpu_count(),
                 cpu_model=model,
                 sample=f"{done} wavelengths x {K} layers of the same workload, forward + loss + "
-                       f"adjoint, numpy.fft (pocketfft, single thread) FP64, {dt:.1f} s")
+                       f"adjoint, FP64 oracle with numpy.fft (pocketfft), one wavelength per host "
+                       f"thread, {threads} threads, {dt:.1f} s")
 
 
 def traffic_from_profiles(pass_name):
@@ -171,6 +188,11 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=1,
                     help="timed training epochs (128-wavelength batches + Adam) after the step; 0 skips")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the oracle baseline (0: the CPUs this process may use, at most 16)")
+    ap.add_argument("--graph-reps", type=int, default=20,
+                    help="steps replayed from HIP graphs after the timed region (a second plan with "
+                         "use_graph); 0 skips them")
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-loop", action="store_true")
@@ -260,12 +282,16 @@ def main():
     ms_step = ev0.elapsed_time(ev1) / args.steps
     value = props / (ms_step / 1e3)
 
-    # dominant kernel: the pass with the largest summed time.  Its bound is arithmetic (the
-    # column pass issues vector instructions about 80% of its cycles, rocprofv3 counters), so
-    # the roofline is taken against the FP32 vector peak at the conventional 5 M log2 M flop
-    # count of each transform; the HBM rate of the same launches is reported beside it.
-    dom = max(passes, key=lambda k: passes[k]["ms"])
-    pd = passes[dom]
+    # dominant kernel: the kernel instance with the largest summed time (the full-plane column
+    # passes are one instance each; the last forward and first adjoint column passes, which
+    # read or keep only the window rows, are another).  The roofline is the HBM one: algorithmic
+    # bytes per launch over the average launch time of that instance, against 8 TB/s.  The
+    # pass issues vector instructions most of its cycles (rocprofv3 counters), so the same
+    # launches are also given against the FP32 issue ceiling of a build without packed FP32
+    # (78.6 TFLOP/s) at the conventional 5 M log2 M flops per transform.
+    inst = {k: passes[k] for k in INSTANCE_PASSES if k in passes and passes[k]["launches"]}
+    dom = max(inst, key=lambda k: inst[k]["ms"])
+    pd = inst[dom]
     nl = max(pd["launches"], 1)
     per_launch_s = pd["ms"] / 1e3 / nl
     bytes_per_launch = pd["bytes"] / nl
@@ -273,18 +299,21 @@ def main():
     tfs = flops_per_launch / per_launch_s / 1e12
     gbs = bytes_per_launch / per_launch_s / 1e9
     traffic = traffic_from_profiles(dom)
-    roofline = dict(bound="alu", kernel=dom, achieved=round(tfs, 2), peak=FP32_VECTOR_PEAK_TFS,
-                    unit="TFLOP/s", frac=round(tfs / FP32_VECTOR_PEAK_TFS, 4), traffic=traffic,
-                    algorithmic_flops_per_launch=flops_per_launch,
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic,
                     algorithmic_bytes_per_launch=int(bytes_per_launch),
-                    hbm=dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=round(gbs / HBM_PEAK_GBS, 4)),
-                    avg_launch_ms=round(per_launch_s * 1e3, 4), launches=pd["launches"])
+                    avg_launch_ms=round(per_launch_s * 1e3, 4), launches=pd["launches"],
+                    alu=dict(achieved=round(tfs, 2), peak=FP32_NONPACKED_PEAK_TFS, unit="TFLOP/s",
+                             frac=round(tfs / FP32_NONPACKED_PEAK_TFS, 4),
+                             algorithmic_flops_per_launch=flops_per_launch,
+                             peak_note="FP32 without packed instructions; the published 157.3 counts "
+                                       "packed FP32"))
     pass_summary = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3),
+                            ms_per_launch=round(v["ms"] / v["launches"], 4),
                             gbs=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
                             tflops=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["ms"] > 0 else None)
                     for k, v in passes.items() if v["launches"]}
-    all_bytes = sum(v["bytes"] for v in passes.values())
+    all_bytes = sum(v["bytes"] for k, v in passes.items() if k not in AGGREGATE_ONLY)
     step_gbs = all_bytes / args.steps / (ms_step / 1e3) / 1e9
 
     # after the timed region: the spread of single steps, a forward-only rate, and the device
@@ -324,6 +353,29 @@ def main():
                     ms_median=round(pick(mis_ms, 0.5), 3),
                     vs_aligned=round(pick(mis_ms, 0.5) / pick(steps_ms, 0.5), 3),
                     offsets="layers displaced U(+-40 nm) laterally, U(+-200 nm) axially")
+        if args.graph_reps > 0 and not args.graph:
+            # the same step replayed from HIP graphs (a second plan that captures each call once)
+            gplan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
+                             force_variant=args.variant, autotune=args.autotune, streams=args.streams,
+                             use_graph=True, schedule=args.schedule, transfer_table=args.transfer_table,
+                             small_path=args.small_path)
+
+            def gstep():
+                gplan.forward(h, u, I)
+                gplan.loss(I, tau, L, g)
+                gplan.backward(h, u, g, dh)
+            for _ in range(2):
+                gstep()
+            torch.cuda.synchronize()
+            g_ms = sorted(timed(gstep) for _ in range(args.graph_reps))
+            extra["graph_step"] = dict(ms_median=round(pick(g_ms, 0.5), 3), p10=round(pick(g_ms, 0.1), 3),
+                                       p90=round(pick(g_ms, 0.9), 3), reps=args.graph_reps,
+                                       vs_eager=round(pick(g_ms, 0.5) / pick(steps_ms, 0.5), 4),
+                                       value=round(props / (pick(g_ms, 0.5) / 1e3), 1))
+            gplan.close()
+            del gplan
+            torch.cuda.empty_cache()
+            log(f"[bench] {args.graph_reps} graph replays of the step done")
         n = (1 << 30) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -376,8 +428,14 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline and len(designs) == 1:
-        log(f"[bench] FP64 oracle on the host for about {args.cpu_seconds:.0f} s")
-        cpu = cpu_baseline(designs[0], w["h"][0], w["targets"][0], args.cpu_seconds, u_in=w["u_in"][0])
+        # the host share of one GPU is 16 CPUs on the boxes this runs on, whatever the count of
+        # visible CPUs says
+        threads = args.cpu_threads or max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"[bench] FP64 oracle on {threads} host threads for about {args.cpu_seconds:.0f} s")
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=threads) as pool:
+            cpu = cpu_baseline(designs[0], w["h"][0], w["targets"][0], args.cpu_seconds, u_in=w["u_in"][0],
+                               pool=pool, threads=threads)
         cpu["value"] = round(cpu["value"], 3)
 
     d0 = designs[0]
