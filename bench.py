@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 3, 4, 5, 6])
+    ap.add_argument("--wavelengths", type=int, default=0,
+                    help="profiling aid: keep only the first N wavelengths of each design (0: all)")
     ap.add_argument("--checkpoint-mode", type=int, default=0, choices=[0, 1])
     ap.add_argument("--wl-chunk", type=int, default=0)
     ap.add_argument("--streams", type=int, default=0, help="concurrent chunk lanes (0 automatic)")
@@ -215,6 +217,13 @@ def main():
     torch.cuda.set_device(dev)
     log(f"[bench] workload {args.workload}: {WORKLOAD_NAMES[args.workload]}")
     w = wk.make_workload(args.workload)
+    if args.wavelengths > 0:
+        # profiling runs: the first wavelengths of every design only (same kernels, shorter launches)
+        for i, d in enumerate(w["designs"]):
+            k = min(args.wavelengths, d["n_wl"])
+            w["designs"][i] = wk.subset_wavelengths(d, range(k))
+            w["targets"][i] = w["targets"][i][:k]
+        log(f"[bench] first {args.wavelengths} wavelengths of each design only")
     designs = w["designs"]
     plan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
                     force_variant=args.variant, autotune=args.autotune, streams=args.streams,
@@ -443,7 +452,9 @@ def main():
         metric=METRIC, value=round(value, 1), unit=UNIT, n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload=WORKLOAD_NAMES[args.workload], designs=len(designs),
+        config=dict(workload=WORKLOAD_NAMES[args.workload] +
+                    (f" (first {args.wavelengths} wavelengths only)" if args.wavelengths > 0 else ""),
+                    designs=len(designs),
                     wavelengths=sum(d["n_wl"] for d in designs), layers=d0["layers"], n=d0["n"],
                     transform=d0["n"] * d0["pad"], checkpoint_mode=args.checkpoint_mode,
                     wl_chunk=args.wl_chunk, streams=args.streams, graph=args.graph,

@@ -764,7 +764,8 @@ void add_col_position(dpx_plan* p, const std::vector<ColItem>& items, bool conj,
       tasks.push_back(t);
       nb.push_back(t.nblocks);
       // column tiles pair up on an XCD in runs of 16 blocks counted from the task's start
-      al.push_back(t.gx % 16 == 0 ? 16 : 1);
+      // (col_block_item), which needs an even tile count
+      al.push_back(t.gx % 2 == 0 ? 16 : 1);
       by.push_back(col_bytes(d, d.W, it.in_lo, it.in_hi, it.out_lo, it.out_hi));
       ub.push_back(0);
       fl.push_back(col_flops(d, d.W));

@@ -341,12 +341,34 @@ template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX
 template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 5, RX = 0, CX = 4;  static constexpr int R[4] = {16, 16, 4, 0}; };
 template <> struct Plan<1600> { static constexpr int E = 20, NST = 3, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {20, 20, 4, 0}; };
 
+// Block padding of the exchanges of a plan: where A[s] > 0, the exchange after stage s stores
+// index i at i + (i / A[s]) B[s] (B[s] padding slots after every A[s] entries) instead of the
+// shift padding of Plan::SH; REGION then is the exchange region of every transform and SKEW the
+// offset of the staged column rows of tile column c, SKEW (c / 2) slots into its region.  A[s]
+// is a multiple of both P and the span NS R of the stage's butterflies, so every lane's writes
+// and reads stay a lane base plus compile-time offsets.  Chosen with the same 64-bank model as
+// the shift paddings: for the 1600-point transform, whose 80-lane groups span wavefronts, the
+// shift padding left about half of the exchange cycles in bank conflicts.
+template <int M>
+struct XPad {
+  static constexpr int A[4] = {0, 0, 0, 0};
+  static constexpr int B[4] = {0, 0, 0, 0};
+  static constexpr int REGION = 0;
+  static constexpr int SKEW = 0;
+};
+template <> struct XPad<1600> {
+  static constexpr int A[4] = {160, 400, 0, 0};
+  static constexpr int B[4] = {1, 4, 0, 0};
+  static constexpr int REGION = 1616;
+  static constexpr int SKEW = 4;
+};
+
 template <int M>
 struct Geo {
   static constexpr int E = Plan<M>::E;
   static constexpr int P = M / E;  // lanes per transform
-  static constexpr int ROW_REGION = M + (M >> Plan<M>::SH) + Plan<M>::RX;
-  static constexpr int COL_REGION = M + (M >> Plan<M>::SH) + Plan<M>::CX;
+  static constexpr int ROW_REGION = XPad<M>::REGION > 0 ? XPad<M>::REGION : M + (M >> Plan<M>::SH) + Plan<M>::RX;
+  static constexpr int COL_REGION = XPad<M>::REGION > 0 ? XPad<M>::REGION : M + (M >> Plan<M>::SH) + Plan<M>::CX;
   // the lanes of one transform lie in one wavefront
   static constexpr bool WAVE_LOCAL = P <= 64 && 64 % P == 0;
   static_assert(WAVE_LOCAL || P % 16 == 0, "a group spanning wavefronts is a whole number of 16-lane rows");
@@ -416,7 +438,10 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
   constexpr int S2 = 1 << SH;
   constexpr bool LIN_W = divides_or_multiple(NS, S2) && divides_or_multiple(NS * R, S2);
   constexpr bool LIN_R = (P % S2 == 0);
+  constexpr int XA = XPad<M>::A[ST];
+  constexpr int XB = XPad<M>::B[ST];
   static_assert(E % R == 0, "radix must divide the registers per lane");
+  static_assert(XA == 0 || LAST || (XA % P == 0 && XA % (NS * R) == 0), "block padding must keep lanes linear");
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int j = j0 + P * s;
@@ -438,7 +463,12 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
       for (int r = 0; r < R; ++r) reg[s + r * S] = v[r];
     } else {
       const int b0 = (j / NS) * NS * R;
-      if constexpr (LIN_W) {
+      if constexpr (XA > 0) {
+        // b0 + k + r NS stays inside one padding block (XA is a multiple of NS R)
+        const int lane_base = b0 + k + (b0 / XA) * XB;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lane_base + r * NS] = v[r];
+      } else if constexpr (LIN_W) {
         const int lane_base = b0 + (b0 >> SH) + k + (k >> SH);
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[lane_base + r * NS + ((r * NS) >> SH)] = v[r];
@@ -450,7 +480,11 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
   }
   if constexpr (!LAST) {
     group_sync<M>();
-    if constexpr (LIN_R) {
+    if constexpr (XA > 0) {
+      // j0 + P t: j0 < P and XA is a multiple of P, so the block is that of P t
+#pragma unroll
+      for (int t = 0; t < E; ++t) reg[t] = lds[j0 + P * t + ((P * t) / XA) * XB];
+    } else if constexpr (LIN_R) {
       const int rb = j0 + (j0 >> SH);
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = lds[rb + P * t + ((P * t) >> SH)];

@@ -308,10 +308,25 @@ __device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
 // the phase; the band-limited spectrum evaluates every element inside the band.
 constexpr int kHEval = 0, kHMirror = 1, kHTable = 2, kHShift = 3, kHBand = 4;
 
-// Block (bx, by) of a column pass: column tile bx of gx, wavelength block by.  The blocks of
-// one pass are numbered bx + gx by from a multiple of 16 in launch order.
+// XCD-aware order of a column pass's blocks.  Consecutive blocks go to the eight XCDs in turn,
+// so blocks L and L + 8 of every run of 16 share an XCD and its L2; they take neighbouring
+// column tiles of the same wavelength block, so the two halves of each 128-byte row segment
+// meet in one L2 instead of being fetched twice.  Blocks are numbered L = bx + gx by from a
+// multiple of 16 in launch order; with an even tile count gx a pair never straddles two
+// wavelength blocks; a tail of fewer than 16 blocks keeps its order.
+__device__ __forceinline__ void col_block_item(int L, int total, int gx, int& bx, int& by) {
+  int item = L;
+  if ((gx & 1) == 0 && L < (total & ~15)) {
+    const int r = L & 15;
+    item = (L & ~15) + ((r & 7) << 1) + (r >> 3);
+  }
+  bx = item % gx;
+  by = item / gx;
+}
+
+// Block (bx, by) of a column pass: column tile bx, wavelength block by.
 template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL>
-__device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int gx, float2* tile, float2* tw) {
+__device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float2* tile, float2* tw) {
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
   constexpr int NT = TX * P;
@@ -321,15 +336,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
   static_assert(NT / TX == P, "staging rows per pass");
 
   const int N = M / PAD;
-  // XCD-aware tile order: consecutive blocks go to the eight XCDs in turn, so blocks b and
-  // b + 8 of every run of 16 share an XCD and its L2; giving them neighbouring column tiles
-  // lets the two halves of each 128-byte row segment meet in the same L2.
-  int tile_x = bx;
-  if ((gx & 15) == 0) {
-    const int r = tile_x & 15;
-    tile_x = (tile_x & ~15) + ((r & 7) << 1) + (r >> 3);
-  }
-  const int kx0 = tile_x * TX;
+  const int kx0 = bx * TX;
   const int cc = threadIdx.x % TX;
   const int yy = threadIdx.x / TX;
   const int g = threadIdx.x / P;
@@ -337,6 +344,11 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
   float2* lds = tile + g * LD;
   const int kx = kx0 + g;
   const int kxs = kx < M / 2 ? kx : kx - M;
+  // staged rows of tile column c start SKEW (c / 2) slots into its region (bank spread of the
+  // staging with block-padded regions); the transforms' exchanges use the region from slot 0
+  constexpr int SKEW = XPad<M>::SKEW;
+  float2* lds_in = lds + SKEW * (g >> 1);
+  float2* stg = tile + cc * LD + SKEW * (cc >> 1);
 
   // The block runs a.col_wpb wavelengths.  With zero padding the staged rows of the next one
   // are loaded into registers while the current one is transformed, so their latency is
@@ -370,7 +382,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
       const int y = in_lo + yy + k * P;
       pre[PREFETCH ? k : 0] = (y < in_hi) ? buffer_load_c64(rs, voff, k * P * M * 8) : make_float2(0.f, 0.f);
       if constexpr (!PREFETCH) {
-        if (y < in_hi) tile[cc * LD + y] = pre[0];
+        if (y < in_hi) stg[y] = pre[0];
       }
     }
   };
@@ -378,7 +390,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
 #pragma unroll
     for (int k = 0; k < EN; ++k) {
       const int y = in_lo + yy + k * P;
-      if (y < in_hi) tile[cc * LD + y] = pre[k];
+      if (y < in_hi) stg[y] = pre[k];
     }
   };
   // With every row in and out, the tile elements a thread stages for the next wavelength are
@@ -404,7 +416,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
       const int y = j0 + P * t;
-      reg[t] = (y >= in_lo && y < in_hi) ? lds[y] : make_float2(0.f, 0.f);
+      reg[t] = (y >= in_lo && y < in_hi) ? lds_in[y] : make_float2(0.f, 0.f);
     }
     group_sync<M>();
     fft<M, false, HALF>(reg, lds, j0, tw);
@@ -485,15 +497,15 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, int g
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
       const int y = j0 + P * t;
-      if (y >= out_lo && y < out_hi) lds[y] = reg[t];
+      if (y >= out_lo && y < out_hi) lds_in[y] = reg[t];
     }
     __syncthreads();
     float2* sp = a.spec + static_cast<size_t>(w) * N * M + kx0 + cc;
     if constexpr (FULL) {
 #pragma unroll
-      for (int k = 0; k < EN; ++k) sp[static_cast<size_t>(yy + k * P) * M] = tile[cc * LD + yy + k * P];
+      for (int k = 0; k < EN; ++k) sp[static_cast<size_t>(yy + k * P) * M] = stg[yy + k * P];
     } else {
-      for (int y = out_lo + yy; y < out_hi; y += P) sp[static_cast<size_t>(y) * M] = tile[cc * LD + y];
+      for (int y = out_lo + yy; y < out_hi; y += P) sp[static_cast<size_t>(y) * M] = stg[y];
     }
     if constexpr (STAGE_AFTER_STORE) {
       if (w + 1 < we) stage();
@@ -508,7 +520,10 @@ __global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_pe
 col_kernel(ColArgs a) {
   __shared__ float2 tile[TX * Geo<M>::COL_REGION];
   __shared__ float2 tw[twiddle_count<M>()];
-  col_body<M, PAD, CONJ, TX, HM, FULL>(a, blockIdx.x, blockIdx.y, gridDim.x, tile, tw);
+  int bx, by;
+  col_block_item(static_cast<int>(blockIdx.x + gridDim.x * blockIdx.y), static_cast<int>(gridDim.x * gridDim.y),
+                 static_cast<int>(gridDim.x), bx, by);
+  col_body<M, PAD, CONJ, TX, HM, FULL>(a, bx, by, tile, tw);
 }
 
 // One launch of a column pass for several designs of the same transform length (see
@@ -523,7 +538,9 @@ col_group_kernel(GroupArgs g) {
   const int local = static_cast<int>(blockIdx.x) - g.block0[ti];
   if (local >= t.nblocks) return;
   const ColArgs a = t.a;
-  col_body<M, PAD, CONJ, TX, HM, FULL>(a, local % t.gx, local / t.gx, t.gx, tile, tw);
+  int bx, by;
+  col_block_item(local, t.nblocks, t.gx, bx, by);
+  col_body<M, PAD, CONJ, TX, HM, FULL>(a, bx, by, tile, tw);
 }
 
 // H / M^2 of one gap for every wavelength on the quarter plane |kx|, |ky| <= M/2 (H depends on
