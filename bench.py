@@ -183,7 +183,9 @@ def main():
                     help="replay HIP graphs of each call (per-pass timers then come from one extra "
                          "direct step after the timed region)")
     ap.add_argument("--variant", type=int, default=-1, help="column-pass variant (-1 automatic)")
-    ap.add_argument("--autotune", action="store_true", help="time column-pass variants at plan creation")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time column-pass variants and radix plans at plan creation")
+    ap.add_argument("--plan", type=int, default=-1, help="radix plan of the transforms (-1 automatic)")
     ap.add_argument("--reps", type=int, default=20,
                     help="single steps and forward calls timed one by one after the timed region "
                          "(median, p10, p90); 0 skips them")
@@ -228,9 +230,12 @@ def main():
     plan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
                     force_variant=args.variant, autotune=args.autotune, streams=args.streams,
                     use_graph=args.graph, schedule=args.schedule, transfer_table=args.transfer_table,
-                    small_path=args.small_path)
+                    small_path=args.small_path, force_plan=args.plan)
     variant = dpx.variant_names()[plan.variant(0)]
-    log(f"[bench] column-pass variant {variant}")
+    M0 = designs[0]["n"] * designs[0]["pad"]
+    plan_names = dpx.radix_plan_names(M0)
+    radix = dict(zip(("row", "column"), (plan_names[k] for k in plan.radix(0))))
+    log(f"[bench] column-pass variant {variant}, radix plans {radix}")
     h = plan.pack_heights(w["h"])
     tau = plan.pack_images(w["targets"])
     # input fields (an aperture) of the designs that have one, unit plane waves elsewhere
@@ -367,7 +372,7 @@ def main():
             gplan = dpx.Plan(designs, checkpoint_mode=args.checkpoint_mode, wl_chunk=args.wl_chunk,
                              force_variant=args.variant, autotune=args.autotune, streams=args.streams,
                              use_graph=True, schedule=args.schedule, transfer_table=args.transfer_table,
-                             small_path=args.small_path)
+                             small_path=args.small_path, force_plan=args.plan)
 
             def gstep():
                 gplan.forward(h, u, I)
@@ -460,7 +465,7 @@ def main():
                     wl_chunk=args.wl_chunk, streams=args.streams, graph=args.graph,
                     schedule={1: "per-design", 2: "grouped"}[plan.schedule()],
                     transfer_tables=plan.has_transfer_tables(), lds_resident=plan.uses_lds_path(),
-                    column_variant=variant,
+                    column_variant=variant, radix_plans=radix,
                     phase_args="f64"),
         roofline=roofline, cpu_baseline=cpu, plain_loop=plain,
         vs_plain_loop=(round(value / plain["value"], 2) if plain else None),

@@ -124,8 +124,14 @@ typedef struct dpx_opts {
                                plan-owned stream ordered after and before the caller's stream
                                by events).  Buffer contents may change between calls; the
                                pointers may not.  Per-pass timers run the launches directly. */
-  int32_t autotune;         /* nonzero: dpx_plan_create times every column-pass variant on
-                               each distinct transform length and keeps the fastest */
+  int32_t autotune;         /* nonzero: dpx_plan_create times every column-pass variant and
+                               radix plan, and the radix plans of the row passes, on each
+                               distinct transform length (up to 256 of a design's wavelengths,
+                               three interleaved rounds) and keeps the fastest.  With the
+                               environment variable DPX_TUNE_CACHE naming a file, the choices
+                               are appended there per (length, pad, band limit, timed
+                               wavelengths) and later plans, in any process, take them from
+                               it without timing. */
   int32_t force_variant;    /* -1: automatic (autotuned if asked, else a built-in choice per
                                transform length); otherwise a column-pass variant index
                                (see dpx_variant_count / dpx_variant_name).  The transform
@@ -178,6 +184,16 @@ typedef struct dpx_opts {
                                and return DPX_E_NONFINITE naming the output and the count.
                                Such calls synchronise, so they cannot be stream-captured.
                                0: no scan, no synchronisation. */
+  int32_t force_plan;       /* radix plan of the transforms (see dpx_radix_plan_count /
+                               dpx_radix_plan_name): -1 = automatic (with autotune, the
+                               fastest plan of each pass kind is timed and kept per design,
+                               else plan 0); k >= 0 = plan k for the row and column passes of
+                               every design (DPX_E_UNSUPPORTED where a transform length has no
+                               plan k).  Plans other than 0 run the per-design schedule with
+                               the evaluated transfer function of untranslated full-spectrum
+                               gaps; a column pass that needs another H source (transfer
+                               tables, band limit, a lateral translation) runs on plan 0.
+                               Different plans agree to rounding, not bit for bit. */
 } dpx_opts;
 
 /* Offsets (in elements of the buffer's type) of one design inside the packed buffers. */
@@ -215,6 +231,15 @@ dpx_status dpx_plan_query(const dpx_design* designs, int32_t n_designs, const dp
 
 /* Releases the plan and its device memory (synchronises the device first). NULL is a no-op. */
 dpx_status dpx_plan_destroy(dpx_plan* plan);
+
+/* Radix plans of the transforms of length M: their count (0 for an unsupported length) and a
+ * name listing the radices of each stage, e.g. "16x16x4" (empty for an unknown plan; valid
+ * until the next call on this thread). */
+int32_t dpx_radix_plan_count(int32_t M);
+const char* dpx_radix_plan_name(int32_t M, int32_t plan);
+
+/* The radix plans design `design` runs: its row passes and its column passes. */
+dpx_status dpx_plan_radix(const dpx_plan* plan, int32_t design, int32_t* row_plan, int32_t* col_plan);
 
 /* Packed-buffer offsets of design `design` (0 <= design < n_designs). */
 dpx_status dpx_plan_layout(const dpx_plan* plan, int32_t design, dpx_layout* out);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <limits>
@@ -66,6 +67,8 @@ struct Design {
   int nslots;        // lanes * slots_per_lane
   int row_group;     // rows per row-pass block
   int col_variant;   // column-pass kernel variant
+  int row_plan = 0;  // radix plans of the row and column transforms
+  int col_plan = 0;
   bool lds = false;  // forward and adjoint as one LDS-resident launch each
   // 1: the input field meets layer 0 directly, so its field after the first transmission,
   // u_in t_0(h), is rebuilt by the last adjoint pass and gets no checkpoint slab
@@ -196,6 +199,7 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
     if (o->max_workspace_bytes < 0) return fail(DPX_E_ARG, "max_workspace_bytes must be >= 0");
     if (o->force_variant < -1 || o->force_variant >= dpx::kColVariants)
       return fail(DPX_E_ARG, "force_variant must be -1 or a variant index below %d", dpx::kColVariants);
+    if (o->force_plan < -1) return fail(DPX_E_ARG, "force_plan must be -1 or a radix plan index");
   }
   for (int i = 0; i < nd; ++i) {
     const dpx_design& d = ds[i];
@@ -226,6 +230,13 @@ dpx_status validate(const dpx_design* ds, int32_t nd, const dpx_opts* o) {
         !dpx::col_variant_supported(M, d.pad, o->force_variant))
       return fail(DPX_E_UNSUPPORTED, "design %d: column variant %d is not built for transform length %d", i,
                   o->force_variant, M);
+    if (o && o->force_plan > 0 && dpx::fft_size_supported(M) && o->force_plan >= dpx::radix_plan_count(M))
+      return fail(DPX_E_UNSUPPORTED, "design %d: transform length %d has %d radix plan(s), no plan %d", i, M,
+                  dpx::radix_plan_count(M), o->force_plan);
+    if (o && o->force_plan > 0 && (d.band_limited || o->transfer_table == 2 || o->schedule == 2 || o->small_path))
+      return fail(DPX_E_UNSUPPORTED,
+                  "design %d: radix plans other than 0 run the per-design schedule without transfer "
+                  "tables, band limit or the LDS-resident path", i);
     if (!dpx::fft_size_supported(M))
       return fail(DPX_E_UNSUPPORTED,
                   "design %d: transform length pad*n = %d is not built (64, 96, 128, 192, 256, "
@@ -413,11 +424,21 @@ dpx_status check_outputs(dpx_plan* p, std::initializer_list<OutputSpan> outs, hi
   return DPX_OK;
 }
 
+// key of a twiddle table in dpx_plan::twiddles
+int tw_key(int M, int plan) { return M * 8 + plan; }
+
+// the radix plan a column launch runs: the design's, unless its transfer function comes from a
+// source that only plan 0 has (tables, band limit, translated gaps)
+int col_plan_of(const Design& d, const ColArgs& c) {
+  if (c.htab || c.band_limited || c.sx != 0.0 || c.sy != 0.0) return 0;
+  return d.col_plan;
+}
+
 // launch arguments for chunk [w0, w0 + wc) running on lane `lane`
 RowArgs row_args(const dpx_plan* p, const Design& d, int w0, int wc, int lane) {
   RowArgs a{};
   a.wl = d.d_wl;
-  a.tw = p->twiddles.at(d.M);
+  a.tw = p->twiddles.at(tw_key(d.M, d.row_plan));
   a.n = d.N;
   a.fov = d.F;
   a.bin = d.b;
@@ -510,7 +531,7 @@ dpx_status run_row(dpx_plan* p, const Design& d, int mode, RowArgs a, int row_lo
                 row_bytes(d, mode, a.w_count, nwb, a.accumulate != 0, a.u_in != nullptr),
                 row_flops(d, mode, a.w_count, row_hi - row_lo)};
   DPX_TRY(timer_begin(p, s, t));
-  hipError_t e = dpx::launch_row(d.M, d.pad, mode, a, nrb, nwb, s);
+  hipError_t e = dpx::launch_row(d.M, d.pad, mode, d.row_plan, a, nrb, nwb, s);
   if (e != hipSuccess) return fail(DPX_E_DEVICE, "row pass (mode %d) launch failed: %s", mode, hipGetErrorString(e));
   DPX_TRY(timer_end(p, s, t));
   return DPX_OK;
@@ -521,7 +542,7 @@ ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0
   ColArgs c{};
   c.spec = spec_of_lane(d, lane);
   c.wl = d.d_wl;
-  c.tw = p->twiddles.at(d.M);
+  c.tw = nullptr;  // set below, once the transfer-function source is known
   // layer -1: the input gap (no misalignment, transfer function evaluated in the pass)
   const double md = static_cast<double>(d.M) * d.dx;
   c.zrev = (layer < 0 ? d.z_in : d.z[layer] + d.dz[layer]) / md;
@@ -545,6 +566,7 @@ ColArgs col_args(const dpx_plan* p, const Design& d, int lane, int layer, int w0
   c.col_wpb = (static_cast<int64_t>(wc) * (d.M / 8) >= 2 * 8192) ? 2 : 1;
   const int64_t hs = d.M / 2 + 1;
   c.htab = (d.htab && layer >= 0) ? d.htab + static_cast<int64_t>(d.zslot[layer]) * d.W * hs * hs : nullptr;
+  c.tw = p->twiddles.at(tw_key(d.M, col_plan_of(d, c)));
   return c;
 }
 
@@ -568,7 +590,7 @@ dpx_status run_col(dpx_plan* p, const Design& d, int lane, int layer, bool conj,
   if (in_lo == 0 && in_hi == d.N && out_lo == 0 && out_hi == d.N)
     t.instance = conj ? DPX_PASS_COL_ADJ_FULL : DPX_PASS_COL_FWD_FULL;
   DPX_TRY(timer_begin(p, s, t));
-  hipError_t e = dpx::launch_col(d.M, d.pad, conj, d.col_variant, c, wc, s);
+  hipError_t e = dpx::launch_col(d.M, d.pad, conj, d.col_variant, col_plan_of(d, c), c, wc, s);
   if (e != hipSuccess) return fail(DPX_E_DEVICE, "column pass launch failed: %s", hipGetErrorString(e));
   DPX_TRY(timer_end(p, s, t));
   return DPX_OK;
@@ -799,7 +821,9 @@ void add_simple_group(std::vector<GroupLaunch>& out, GroupKind kind, const std::
 bool groupable(const dpx_plan* p) {
   if (p->opts.checkpoint_mode != 0) return false;
   for (const auto& d : p->designs)
-    if (d.nchunks != 1 || d.lanes != 1 || d.col_variant > 3 || d.z_in > 0.0 || d.band) return false;
+    if (d.nchunks != 1 || d.lanes != 1 || d.col_variant > 3 || d.z_in > 0.0 || d.band || d.row_plan ||
+        d.col_plan)
+      return false;
   return true;
 }
 
@@ -949,7 +973,7 @@ dpx_status run_lds(dpx_plan* p, const Design& d, bool adjoint, const float* h, c
                    float* intensity, const float* dl_di, hipStream_t s) {
   dpx::LdsArgs a{};
   a.wl = d.d_wl;
-  a.tw = p->twiddles.at(d.M);
+  a.tw = p->twiddles.at(tw_key(d.M, 0));
   a.zrev = d.d_zrev;
   a.h = h + d.h_off;
   a.u_in = u_in ? reinterpret_cast<const float2*>(u_in) + d.u_off : nullptr;
@@ -1006,44 +1030,134 @@ dpx_status join_lanes(dpx_plan* p, const Design& d, hipStream_t s) {
 // Times every column-pass variant on the design's first wavelengths (forward column pass
 // of layer 0 on a zeroed spectrum buffer) and keeps the fastest.  All variants produce the
 // same bits, so the choice changes speed only.
-dpx_status autotune_design(dpx_plan* p, Design& d, std::map<int, int>& cache) {
-  const int key = (d.M * 4 + d.pad) * 2 + (d.band ? 1 : 0);
+// Autotuner results: the column variant and the radix plans of a (transform length, pad,
+// band-limit flag, timed chunk) key.  Kept per plan creation, and across processes in the text
+// file named by the environment variable DPX_TUNE_CACHE when it is set (one line per key:
+// "dpx-tune M pad band wc row_plan col_plan col_variant"; lines for lengths, plans or variants
+// this build does not have are ignored).
+struct TuneChoice {
+  int row_plan, col_plan, col_variant;
+};
+using TuneKey = std::array<int, 4>;
+
+void tune_cache_load(std::map<TuneKey, TuneChoice>& cache) {
+  const char* path = std::getenv("DPX_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    int M, pad, band, wc, rp, cp, cv;
+    if (std::sscanf(line, "dpx-tune %d %d %d %d %d %d %d", &M, &pad, &band, &wc, &rp, &cp, &cv) != 7) continue;
+    const int np = dpx::radix_plan_count(M);
+    if (np == 0 || rp < 0 || rp >= np || cp < 0 || cp >= np || !dpx::col_variant_supported(M, pad, cv)) continue;
+    cache[{M, pad, band, wc}] = {rp, cp, cv};
+  }
+  std::fclose(f);
+}
+
+void tune_cache_store(const TuneKey& k, const TuneChoice& c) {
+  const char* path = std::getenv("DPX_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "dpx-tune %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], c.row_plan, c.col_plan,
+               c.col_variant);
+  std::fclose(f);
+}
+
+// Times the column-pass variants and radix plans, and the radix plans of the middle forward row
+// pass, on one chunk of up to 256 of the design's wavelengths (the planes hold zeros; the
+// passes' cost does not depend on the values), and keeps the fastest of each that the plan's
+// options leave free.  The candidates are timed in three interleaved rounds (three launches
+// each) and each keeps its fastest round, so a drift of the clock over the tuning does not
+// favour the candidates timed first; differences between candidates are a few per cent.
+dpx_status autotune_design(dpx_plan* p, Design& d, std::map<TuneKey, TuneChoice>& cache) {
+  const int wc = std::min(std::min(d.W, d.wl_chunk), 256);
+  const TuneKey key{d.M, d.pad, d.band ? 1 : 0, wc};
+  const bool free_variant = p->opts.force_variant < 0;
+  const bool free_plan = p->opts.force_plan < 0 && !p->grouped && !d.band && !d.htab && !d.lds;
   auto it = cache.find(key);
   if (it != cache.end()) {
-    d.col_variant = it->second;
+    if (free_variant) d.col_variant = it->second.col_variant;
+    if (free_plan) {
+      d.row_plan = it->second.row_plan;
+      d.col_plan = it->second.col_plan;
+    }
     return DPX_OK;
   }
-  const int wc = std::min(std::min(d.W, d.wl_chunk), 64);
   DPX_HIP(hipMemset(d.spec, 0, static_cast<size_t>(wc) * d.N * d.M * 8));
   hipEvent_t e0, e1;
   DPX_HIP(hipEventCreate(&e0));
   DPX_HIP(hipEventCreate(&e1));
-  float best = 1e30f;
-  int best_v = d.band ? d.col_variant : dpx::default_col_variant(d.M);
   const bool was_timing = p->timing;
   p->timing = false;
-  for (int v = 0; v < dpx::kColVariants; ++v) {
-    if (!dpx::col_variant_supported(d.M, d.pad, v)) continue;
-    if (v == 4 && !p->dft.count(d.M * 4 + d.pad)) continue;
-    if (d.band && v > 1) continue;
-    d.col_variant = v;
-    DPX_TRY(run_col(p, d, 0, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
+  auto time_it = [&](auto&& launch, float& ms) -> dpx_status {
     DPX_HIP(hipEventRecord(e0, nullptr));
-    for (int r = 0; r < 3; ++r) DPX_TRY(run_col(p, d, 0, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr));
+    for (int r = 0; r < 3; ++r) DPX_TRY(launch());
     DPX_HIP(hipEventRecord(e1, nullptr));
     DPX_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
     DPX_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      best_v = v;
+    return DPX_OK;
+  };
+  const int nplans = free_plan ? dpx::radix_plan_count(d.M) : 1;
+  TuneChoice pick{d.row_plan, d.col_plan, d.col_variant};
+  // column pass: every (radix plan, variant) left free
+  std::vector<std::array<int, 2>> cand;
+  for (int cp = 0; cp < nplans; ++cp)
+    for (int v = 0; v < dpx::kColVariants; ++v) {
+      if (!free_variant && v != d.col_variant) continue;
+      if (!dpx::col_variant_supported(d.M, d.pad, v)) continue;
+      if (v == 4 && (!p->dft.count(d.M * 4 + d.pad) || cp > 0)) continue;  // the matrix form has no radix plan
+      if (d.band && v > 1) continue;
+      cand.push_back({free_plan ? cp : d.col_plan, v});
     }
+  std::vector<float> best(cand.size(), 1e30f);
+  for (int round = 0; round < 4; ++round)   // round 0 warms every candidate up
+    for (size_t c = 0; c < cand.size(); ++c) {
+      d.col_plan = cand[c][0];
+      d.col_variant = cand[c][1];
+      float ms = 0.f;
+      DPX_TRY(time_it([&]() { return run_col(p, d, 0, 0, false, 0, wc, 0, d.N, 0, d.N, nullptr); }, ms));
+      if (round > 0) best[c] = std::min(best[c], ms);
+    }
+  {
+    const size_t c = static_cast<size_t>(std::min_element(best.begin(), best.end()) - best.begin());
+    pick.col_plan = cand[c][0];
+    pick.col_variant = cand[c][1];
   }
+  d.col_variant = pick.col_variant;
+  d.col_plan = pick.col_plan;
+  // row passes: the middle forward pass (heights of zero, no checkpoints) on every radix plan
+  if (free_plan && nplans > 1) {
+    float* hz = nullptr;
+    DPX_TRY(dev_alloc(&hz, static_cast<int64_t>(d.N) * d.N * 4, "autotuner heights"));
+    dpx_status st = hipMemset(hz, 0, static_cast<size_t>(d.N) * d.N * 4) == hipSuccess
+                        ? DPX_OK : fail(DPX_E_DEVICE, "autotuner height clearing failed");
+    RowArgs a = row_args(p, d, 0, wc, 0);
+    a.h = hz;
+    a.store_ckpt = 0;
+    a.layer = 1;
+    std::vector<float> rbest(nplans, 1e30f);
+    for (int round = 0; round < 4 && st == DPX_OK; ++round)
+      for (int rp = 0; rp < nplans && st == DPX_OK; ++rp) {
+        d.row_plan = rp;
+        a.tw = p->twiddles.at(tw_key(d.M, rp));
+        float ms = 0.f;
+        st = time_it([&]() { return run_row(p, d, dpx::ROW_FWD_MID, a, 0, d.N, nullptr); }, ms);
+        if (round > 0) rbest[rp] = std::min(rbest[rp], ms);
+      }
+    (void)hipDeviceSynchronize();
+    hipFree(hz);
+    DPX_TRY(st);
+    pick.row_plan = static_cast<int>(std::min_element(rbest.begin(), rbest.end()) - rbest.begin());
+  }
+  d.row_plan = pick.row_plan;
   p->timing = was_timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  d.col_variant = best_v;
-  cache[key] = best_v;
+  cache[key] = pick;
+  tune_cache_store(key, pick);
   return DPX_OK;
 }
 
@@ -1147,6 +1261,7 @@ void dpx_opts_default(dpx_opts* o) {
   o->transfer_table = 0;
   o->small_path = 0;
   o->max_workspace_bytes = 0;
+  o->force_plan = -1;
 }
 
 const char* dpx_last_error(void) { return g_last_error.c_str(); }
@@ -1164,6 +1279,18 @@ dpx_status dpx_plan_variant(const dpx_plan* p, int32_t i, int32_t* variant) {
   if (i < 0 || i >= static_cast<int>(p->designs.size()))
     return fail(DPX_E_ARG, "design index %d out of range", i);
   *variant = p->designs[i].col_variant;
+  return ok();
+}
+
+int32_t dpx_radix_plan_count(int32_t M) { return dpx::radix_plan_count(M); }
+
+const char* dpx_radix_plan_name(int32_t M, int32_t plan) { return dpx::radix_plan_name(M, plan); }
+
+dpx_status dpx_plan_radix(const dpx_plan* p, int32_t i, int32_t* row_plan, int32_t* col_plan) {
+  if (!p) return fail(DPX_E_ARG, "plan is NULL");
+  if (i < 0 || i >= static_cast<int>(p->designs.size())) return fail(DPX_E_ARG, "design index %d out of range", i);
+  if (row_plan) *row_plan = p->designs[i].row_plan;
+  if (col_plan) *col_plan = p->designs[i].col_plan;
   return ok();
 }
 
@@ -1291,19 +1418,24 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
     }
     p->bytes += d.bytes;
     if ((st = upload_wavelengths(d)) != DPX_OK) break;
-    if (!p->twiddles.count(d.M)) {
+    // the twiddle tables of every radix plan of the length (a few KB each): the autotuner and
+    // a column pass falling back to plan 0 may use any of them
+    for (int pl = 0; pl < dpx::radix_plan_count(d.M) && st == DPX_OK; ++pl) {
+      if (p->twiddles.count(tw_key(d.M, pl))) continue;
       std::vector<float2> tw;
-      dpx::build_twiddle_table(d.M, tw);
+      dpx::build_twiddle_table(d.M, pl, tw);
       float2* dtw = nullptr;
       const int64_t tb = static_cast<int64_t>(tw.size()) * 8;
       if ((st = dev_alloc(&dtw, tb, "twiddles")) != DPX_OK) break;
-      p->twiddles[d.M] = dtw;
+      p->twiddles[tw_key(d.M, pl)] = dtw;
       if (hipMemcpy(dtw, tw.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
         st = fail(DPX_E_DEVICE, "copy of the twiddle table failed");
         break;
       }
       p->bytes += tb;
     }
+    if (st != DPX_OK) break;
+    if (o.force_plan >= 0) d.row_plan = d.col_plan = o.force_plan;
   }
   for (const auto& d : p->designs) {
     p->h_total += static_cast<int64_t>(d.K) * d.N * d.N;
@@ -1386,8 +1518,9 @@ dpx_status dpx_plan_create(const dpx_design* ds, int32_t nd, const dpx_opts* opt
         hipEventCreateWithFlags(&p->ev_gout, hipEventDisableTiming) != hipSuccess)
       st = fail(DPX_E_DEVICE, "graph stream creation failed");
   }
-  if (st == DPX_OK && o.autotune && o.force_variant < 0) {
-    std::map<int, int> cache;
+  if (st == DPX_OK && o.autotune && (o.force_variant < 0 || o.force_plan < 0)) {
+    std::map<TuneKey, TuneChoice> cache;
+    tune_cache_load(cache);
     for (auto& d : p->designs)
       if ((st = autotune_design(p, d, cache)) != DPX_OK) break;
   }

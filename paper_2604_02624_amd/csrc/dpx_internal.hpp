@@ -202,10 +202,12 @@ __device__ __forceinline__ int group_task(const GroupArgs& g, int b) {
 // Supported transform lengths; the pass launchers of each live in their own translation unit.
 #define DPX_FOR_EACH_M(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024) X(1600)
 #define DPX_DECLARE_PASS_LAUNCHERS(m)                                                                   \
-  hipError_t launch_row_##m(int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,       \
-                            hipStream_t s);                                                             \
+  hipError_t launch_row_##m(int pad, int mode, int plan, const RowArgs& a, int n_row_blocks,             \
+                            int n_w_blocks, hipStream_t s);                                             \
   hipError_t launch_row_group_##m(int pad, int mode, const GroupArgs& g, hipStream_t s);                \
-  hipError_t launch_col_##m(int pad, bool conj, int variant, const ColArgs& a, int w_count, hipStream_t s); \
+  hipError_t launch_col_##m(int pad, bool conj, int variant, int plan, const ColArgs& a, int w_count,    \
+                            hipStream_t s);                                                             \
+  void twiddle_table_##m(int plan, std::vector<float2>& out);                                           \
   hipError_t launch_col_group_##m(int pad, bool conj, int variant, bool table, bool full,               \
                                   const GroupArgs& g, hipStream_t s);                                   \
   hipError_t launch_transfer_table_##m(const WlConst* wl, int W, double zrev, float2* out, hipStream_t s); \
@@ -227,7 +229,8 @@ hipError_t launch_dh_group(const GroupArgs& g, float* dl_dh, hipStream_t s);
 int col_tile_width(int M, int variant);  // columns per block of a transform variant (0-3)
 
 // launchers (dpx_kernels.hip); each returns a hipError_t from the launch
-hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,
+// plan: the radix plan of the transforms (0 .. radix_plan_count(M) - 1)
+hipError_t launch_row(int M, int pad, int mode, int plan, const RowArgs& a, int n_row_blocks, int n_w_blocks,
                       hipStream_t s);
 constexpr int kColVariants = 5;
 bool col_variant_supported(int M, int pad, int variant);
@@ -236,7 +239,7 @@ bool col_variant_supported(int M, int pad, int variant);
 void build_dft_table(int M, int pad, std::vector<float2>& out);
 extern const char* const kColVariantNames[kColVariants];
 int default_col_variant(int M);
-hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
+hipError_t launch_col(int M, int pad, bool conj, int variant, int plan, const ColArgs& a, int w_count,
                       hipStream_t s);
 // fills out[w][|kx|][|ky|] (w < W, |kx|, |ky| <= M/2) with H / M^2 of the gap z = zrev M dx,
 // by the same device function the column pass evaluates
@@ -272,7 +275,11 @@ hipError_t launch_psnr(const float* I, const float* tau, double* out, int W, int
 
 bool fft_size_supported(int M);
 // host: per-stage twiddle table of the length-M transform (layout in fft.hpp)
-void build_twiddle_table(int M, std::vector<float2>& out);
+void build_twiddle_table(int M, int plan, std::vector<float2>& out);
+// radix plans of a transform length (plan 0 is the built-in one; the others run the evaluated
+// and mirrored transfer functions of untranslated full-spectrum gaps, per-design schedule only)
+int radix_plan_count(int M);
+const char* radix_plan_name(int M, int plan);
 int row_lanes_per_transform(int M);  // P = M / E
 int row_rows_per_block(int M, int mode);  // rows (transforms) per row-pass block
 

@@ -266,25 +266,6 @@ __global__ void __launch_bounds__(256) count_nonfinite_kernel(const T* __restric
 // ------------------------------------------------------------------------------------------
 // Host-side tables and sizes
 // ------------------------------------------------------------------------------------------
-template <int M>
-static void twiddle_table(std::vector<float2>& out) {
-  out.assign(twiddle_count<M>() > 0 ? twiddle_count<M>() : 1, make_float2(1.f, 0.f));
-  int ns = Plan<M>::R[0];
-  for (int st = 1; st < Plan<M>::NST; ++st) {
-    const int R = Plan<M>::R[st];
-    const int L = ns * R;
-    const int off = twiddle_offset<M>(st);
-    for (int r = 1; r < R; ++r)
-      for (int k = 0; k < ns; ++k) {
-        const double ang = 6.283185307179586476925286766559 * static_cast<double>((r * k) % L) /
-                           static_cast<double>(L);
-        out[off + (r - 1) * ns + k] = make_float2(static_cast<float>(std::cos(ang)),
-                                                  static_cast<float>(-std::sin(ang)));
-      }
-    ns = L;
-  }
-}
-
 void build_dft_table(int M, int pad, std::vector<float2>& out) {
   const int N = M / pad;
   out.assign(static_cast<size_t>(2) * M * N, make_float2(0.f, 0.f));
@@ -298,14 +279,41 @@ void build_dft_table(int M, int pad, std::vector<float2>& out) {
     }
 }
 
-void build_twiddle_table(int M, std::vector<float2>& out) {
+void build_twiddle_table(int M, int plan, std::vector<float2>& out) {
   switch (M) {
-#define DPX_CASE(m) case m: twiddle_table<m>(out); return;
+#define DPX_CASE(m) case m: twiddle_table_##m(plan, out); return;
     DPX_FOR_EACH_M(DPX_CASE)
 #undef DPX_CASE
     default:
       out.clear();
   }
+}
+int radix_plan_count(int M) { return fft_size_supported(M) ? radix_plans(M) : 0; }
+template <int m, int v>
+static void radix_name(char* buf, size_t cap) {
+  int n = 0;
+  for (int st = 0; st < Radix<m, v>::NST; ++st)
+    n += snprintf(buf + n, cap - n, st ? "x%d" : "%d", Radix<m, v>::R[st]);
+}
+// "16x16x4": the radices of plan `plan` of length M (empty for an unknown pair)
+const char* radix_plan_name(int M, int plan) {
+  static thread_local char buf[32];
+  buf[0] = 0;
+  if (plan < 0 || plan >= radix_plan_count(M)) return buf;
+  switch (M) {
+#define DPX_CASE(m) \
+  case m:           \
+    if (plan == 0) radix_name<m, 0>(buf, sizeof(buf)); \
+    break;
+    DPX_FOR_EACH_M(DPX_CASE)
+#undef DPX_CASE
+    default: break;
+  }
+  if (M == 512 && plan == 1) radix_name<512, 1>(buf, sizeof(buf));
+  if (M == 512 && plan == 2) radix_name<512, 2>(buf, sizeof(buf));
+  if (M == 1024 && plan == 1) radix_name<1024, 1>(buf, sizeof(buf));
+  if (M == 1024 && plan == 2) radix_name<1024, 2>(buf, sizeof(buf));
+  return buf;
 }
 
 bool fft_size_supported(int M) {
@@ -375,10 +383,10 @@ int col_tile_width(int M, int variant) {
 // ------------------------------------------------------------------------------------------
 // Dispatch to the per-length launchers
 // ------------------------------------------------------------------------------------------
-hipError_t launch_row(int M, int pad, int mode, const RowArgs& a, int n_row_blocks, int n_w_blocks,
+hipError_t launch_row(int M, int pad, int mode, int plan, const RowArgs& a, int n_row_blocks, int n_w_blocks,
                       hipStream_t s) {
   switch (M) {
-#define DPX_CASE(m) case m: return launch_row_##m(pad, mode, a, n_row_blocks, n_w_blocks, s);
+#define DPX_CASE(m) case m: return launch_row_##m(pad, mode, plan, a, n_row_blocks, n_w_blocks, s);
     DPX_FOR_EACH_M(DPX_CASE)
 #undef DPX_CASE
     default:
@@ -397,11 +405,11 @@ hipError_t launch_row_group(int M, int pad, int mode, const GroupArgs& g, hipStr
   }
 }
 
-hipError_t launch_col(int M, int pad, bool conj, int variant, const ColArgs& a, int w_count,
+hipError_t launch_col(int M, int pad, bool conj, int variant, int plan, const ColArgs& a, int w_count,
                       hipStream_t s) {
   if (!col_variant_supported(M, pad, variant)) return hipErrorInvalidValue;
   switch (M) {
-#define DPX_CASE(m) case m: return launch_col_##m(pad, conj, variant, a, w_count, s);
+#define DPX_CASE(m) case m: return launch_col_##m(pad, conj, variant, plan, a, w_count, s);
     DPX_FOR_EACH_M(DPX_CASE)
 #undef DPX_CASE
     default:

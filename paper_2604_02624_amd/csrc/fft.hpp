@@ -19,8 +19,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 namespace dpx {
 
@@ -338,8 +340,27 @@ template <> struct Plan<192>  { static constexpr int E = 12, NST = 3, SH = 3, RX
 template <> struct Plan<256>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 8;  static constexpr int R[4] = {16, 16, 0, 0}; };
 template <> struct Plan<384>  { static constexpr int E = 12, NST = 4, SH = 5, RX = 4, CX = 0;  static constexpr int R[4] = {12, 4, 4, 2}; };
 template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX = 16, CX = 16; static constexpr int R[4] = {8, 8, 8, 0}; };
-template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 5, RX = 0, CX = 4;  static constexpr int R[4] = {16, 16, 4, 0}; };
+template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 5, RX = 0, CX = 4;  static constexpr int R[4] = {8, 8, 16, 0}; };
 template <> struct Plan<1600> { static constexpr int E = 20, NST = 3, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {20, 20, 4, 0}; };
+
+// Radix plans: plan 0 of every length is Plan<M>::R; the lengths of the large workloads have
+// alternatives with the same registers per lane (so the same lanes, blocks and LDS regions),
+// chosen per pass by the autotuner.  Transforms of different radix plans round differently but
+// compute the same DFT.  At 1024, 8 x 8 x 16 is the built-in plan: on the large workload it runs
+// the column and row passes about 1 % faster than 16 x 16 x 4 (plan 1) and 2 % faster than
+// 4 x 16 x 16 (plan 2).
+template <int M, int V>
+struct Radix {
+  static_assert(V == 0, "no such radix plan");
+  static constexpr int NST = Plan<M>::NST;
+  static constexpr int R[4] = {Plan<M>::R[0], Plan<M>::R[1], Plan<M>::R[2], Plan<M>::R[3]};
+};
+template <> struct Radix<512, 1>  { static constexpr int NST = 3; static constexpr int R[4] = {16, 16, 2, 0}; };
+template <> struct Radix<512, 2>  { static constexpr int NST = 3; static constexpr int R[4] = {4, 8, 16, 0}; };
+template <> struct Radix<1024, 1> { static constexpr int NST = 3; static constexpr int R[4] = {16, 16, 4, 0}; };
+template <> struct Radix<1024, 2> { static constexpr int NST = 3; static constexpr int R[4] = {4, 16, 16, 0}; };
+// number of radix plans of a length
+constexpr int radix_plans(int M) { return (M == 512 || M == 1024) ? 3 : 1; }
 
 // Block padding of the exchanges of a plan: where A[s] > 0, the exchange after stage s stores
 // index i at i + (i / A[s]) B[s] (B[s] padding slots after every A[s] entries) instead of the
@@ -377,17 +398,38 @@ struct Geo {
 // Per-stage twiddle table: stage s (radix R, NS = product of the earlier radices, s >= 1)
 // stores W_{NS R}^{r k} = exp(-2 pi i r k / (NS R)) at twiddle_offset(s) + (r - 1) NS + k for
 // r = 1..R-1, k = 0..NS-1, so that the lanes of one butterfly row read consecutive entries.
-template <int M>
+template <int M, int V = 0>
 constexpr int twiddle_offset(int stage) {
   int off = 0, ns = 1;
   for (int s = 0; s < stage; ++s) {
-    if (s > 0) off += (Plan<M>::R[s] - 1) * ns;
-    ns *= Plan<M>::R[s];
+    if (s > 0) off += (Radix<M, V>::R[s] - 1) * ns;
+    ns *= Radix<M, V>::R[s];
   }
   return off;
 }
-template <int M>
-constexpr int twiddle_count() { return twiddle_offset<M>(Plan<M>::NST); }
+template <int M, int V = 0>
+constexpr int twiddle_count() { return twiddle_offset<M, V>(Radix<M, V>::NST); }
+
+// The table of radix plan V of length M, built on the host in double precision from exact
+// integer indices: W_L^(r k) with the exponent reduced mod L before the angle is formed.
+template <int M, int V>
+inline void twiddle_table_host(std::vector<float2>& out) {
+  out.assign(twiddle_count<M, V>() > 0 ? twiddle_count<M, V>() : 1, make_float2(1.f, 0.f));
+  int ns = Radix<M, V>::R[0];
+  for (int st = 1; st < Radix<M, V>::NST; ++st) {
+    const int R = Radix<M, V>::R[st];
+    const int L = ns * R;
+    const int off = twiddle_offset<M, V>(st);
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < ns; ++k) {
+        const double ang = 6.283185307179586476925286766559 * static_cast<double>((r * k) % L) /
+                           static_cast<double>(L);
+        out[off + (r - 1) * ns + k] = make_float2(static_cast<float>(std::cos(ang)),
+                                                  static_cast<float>(-std::sin(ang)));
+      }
+    ns = L;
+  }
+}
 
 template <int M>
 __device__ __forceinline__ int lds_slot(int i) {
@@ -395,10 +437,10 @@ __device__ __forceinline__ int lds_slot(int i) {
 }
 
 // Copies the per-stage twiddle table from global memory into LDS (caller synchronises).
-template <int M>
+template <int M, int V = 0>
 __device__ __forceinline__ void stage_twiddles(float2* __restrict__ dst, const float2* __restrict__ src,
                                                int tid, int nthreads) {
-  for (int i = tid; i < twiddle_count<M>(); i += nthreads) dst[i] = src[i];
+  for (int i = tid; i < twiddle_count<M, V>(); i += nthreads) dst[i] = src[i];
 }
 
 // LDS ordering between the lanes of one transform.  A transform never spans more than one
@@ -428,7 +470,7 @@ constexpr bool divides_or_multiple(int a, int b) { return a % b == 0 || b % a ==
 // of the padding period 2^SH, the padded address of output r splits exactly into a per-lane
 // base plus a compile-time offset, and the reads j0 + P t split the same way when P is a
 // multiple of 2^SH; the other stages compute the padded address directly.
-template <int M, int ST, int R, int NS, bool LAST, bool INV, bool HALF>
+template <int M, int V, int ST, int R, int NS, bool LAST, bool INV, bool HALF>
 __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds,
                                                int j0, const float2* __restrict__ tw) {
   constexpr int E = Geo<M>::E;
@@ -438,8 +480,8 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
   constexpr int S2 = 1 << SH;
   constexpr bool LIN_W = divides_or_multiple(NS, S2) && divides_or_multiple(NS * R, S2);
   constexpr bool LIN_R = (P % S2 == 0);
-  constexpr int XA = XPad<M>::A[ST];
-  constexpr int XB = XPad<M>::B[ST];
+  constexpr int XA = V == 0 ? XPad<M>::A[ST] : 0;
+  constexpr int XB = V == 0 ? XPad<M>::B[ST] : 0;
   static_assert(E % R == 0, "radix must divide the registers per lane");
   static_assert(XA == 0 || LAST || (XA % P == 0 && XA % (NS * R) == 0), "block padding must keep lanes linear");
 #pragma unroll
@@ -450,7 +492,7 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = reg[s + r * S];
     if constexpr (NS > 1) {
-      constexpr int OFF = twiddle_offset<M>(ST);
+      constexpr int OFF = twiddle_offset<M, V>(ST);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         const float2 w = tw[OFF + (r - 1) * NS + k];
@@ -496,29 +538,29 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
   }
 }
 
-template <int M, int ST, int NS, bool INV, bool HALF>
+template <int M, int V, int ST, int NS, bool INV, bool HALF>
 __device__ __forceinline__ void fft_stages(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
                                            const float2* __restrict__ tw) {
-  if constexpr (ST < Plan<M>::NST) {
-    constexpr int R = Plan<M>::R[ST];
-    constexpr bool LAST = (ST + 1 == Plan<M>::NST);
-    stockham_stage<M, ST, R, NS, LAST, INV, HALF && ST == 0>(reg, lds, j0, tw);
-    fft_stages<M, ST + 1, NS * R, INV, false>(reg, lds, j0, tw);
+  if constexpr (ST < Radix<M, V>::NST) {
+    constexpr int R = Radix<M, V>::R[ST];
+    constexpr bool LAST = (ST + 1 == Radix<M, V>::NST);
+    stockham_stage<M, V, ST, R, NS, LAST, INV, HALF && ST == 0>(reg, lds, j0, tw);
+    fft_stages<M, V, ST + 1, NS * R, INV, false>(reg, lds, j0, tw);
   }
 }
 
-// Full length-M transform of the group's registers.  HALF: elements M/2..M-1 are zero
-// (zero-padded input); only used when the first radix is even.  tw: the per-stage twiddle
-// table (in LDS).
-template <int M, bool INV, bool HALF>
+// Full length-M transform of the group's registers with radix plan V.  HALF: elements
+// M/2..M-1 are zero (zero-padded input); only used when the first radix is even.  tw: the
+// plan's per-stage twiddle table (in LDS).
+template <int M, bool INV, bool HALF, int V = 0>
 __device__ __forceinline__ void fft(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
                                     const float2* __restrict__ tw) {
-  constexpr bool H = HALF && (Plan<M>::R[0] % 2 == 0);
+  constexpr bool H = HALF && (Radix<M, V>::R[0] % 2 == 0);
   if constexpr (HALF && !H) {
 #pragma unroll
     for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);
   }
-  fft_stages<M, 0, 1, INV, H>(reg, lds, j0, tw);
+  fft_stages<M, V, 0, 1, INV, H>(reg, lds, j0, tw);
 }
 
 }  // namespace dpx

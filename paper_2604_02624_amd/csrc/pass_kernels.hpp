@@ -51,7 +51,7 @@ constexpr int row_block_threads() { return row_threads_for(Geo<M>::P, MODE); }
 // ------------------------------------------------------------------------------------------
 // Block (bx, by) of a row pass: rows row_lo + bx G .. + G - 1, wavelength block by.
 // lds_all: G exchange regions; tw: room for the twiddle table (both in LDS).
-template <int M, int PAD, int MODE>
+template <int M, int PAD, int MODE, int V = 0>
 __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float2* lds_all, float2* tw) {
   constexpr int kRowThreads = row_block_threads<M, MODE>();
   constexpr int E = Geo<M>::E;
@@ -60,7 +60,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
   constexpr int EN = E / PAD;  // registers that hold x < N
   constexpr bool HALF = (PAD == 2);
   constexpr int RG = Geo<M>::ROW_REGION;
-  stage_twiddles<M>(tw, a.tw, threadIdx.x, kRowThreads);
+  stage_twiddles<M, V>(tw, a.tw, threadIdx.x, kRowThreads);
   __syncthreads();
 
   const int N = M / PAD;
@@ -106,7 +106,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
       }
-      fft<M, false, HALF>(reg, lds, j0, tw);
+      fft<M, false, HALF, V>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
 #pragma unroll
@@ -121,7 +121,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false>(reg, lds, j0, tw);
+      fft<M, true, false, V>(reg, lds, j0, tw);
 #pragma unroll
       for (int t = 0; t < EN; ++t) reg[t] = cmul(reg[t], transmission(hreg[t], c));
       if (a.store_ckpt && active) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
       }
-      fft<M, false, HALF>(reg, lds, j0, tw);
+      fft<M, false, HALF, V>(reg, lds, j0, tw);
       if (active) {
 #pragma unroll
         for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
@@ -145,7 +145,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false>(reg, lds, j0, tw);
+      fft<M, true, false, V>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.ofov + static_cast<size_t>(wc) * F * F + static_cast<size_t>(y - x0) * F;
 #pragma unroll
@@ -173,7 +173,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
           reg[t] = make_float2(0.f, 0.f);
         }
       }
-      fft<M, false, HALF>(reg, lds, j0, tw);
+      fft<M, false, HALF, V>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
 #pragma unroll
@@ -200,7 +200,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false>(reg, lds, j0, tw);
+      fft<M, true, false, V>(reg, lds, j0, tw);
       const float ct = static_cast<float>(c.ct);
       const float ca = static_cast<float>(c.ca);
 #pragma unroll
@@ -220,7 +220,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
         if constexpr (MODE == ROW_ADJ_MID) reg[t] = cmulc(gv, transmission(hreg[t], c));
       }
       if constexpr (MODE == ROW_ADJ_MID) {
-        fft<M, false, HALF>(reg, lds, j0, tw);
+        fft<M, false, HALF, V>(reg, lds, j0, tw);
         if (active) {
 #pragma unroll
           for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
@@ -242,11 +242,11 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
   }
 }
 
-template <int M, int PAD, int MODE>
+template <int M, int PAD, int MODE, int V = 0>
 __global__ void __launch_bounds__((row_block_threads<M, MODE>())) row_kernel(RowArgs a) {
   __shared__ float2 lds_all[row_block_threads<M, MODE>() / Geo<M>::P * Geo<M>::ROW_REGION];
-  __shared__ float2 tw[twiddle_count<M>()];
-  row_body<M, PAD, MODE>(a, blockIdx.x, blockIdx.y, lds_all, tw);
+  __shared__ float2 tw[twiddle_count<M, V>()];
+  row_body<M, PAD, MODE, V>(a, blockIdx.x, blockIdx.y, lds_all, tw);
 }
 
 // The same pass with at least three wavefronts per SIMD (a cap of 168 registers): the forward
@@ -325,7 +325,7 @@ __device__ __forceinline__ void col_block_item(int L, int total, int gx, int& bx
 }
 
 // Block (bx, by) of a column pass: column tile bx, wavelength block by.
-template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL>
+template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL, int V = 0>
 __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float2* tile, float2* tw) {
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
@@ -398,7 +398,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
   // without a barrier between them.
   constexpr bool STAGE_AFTER_STORE = FULL && PREFETCH;
   if constexpr (PREFETCH) fetch(wb);
-  stage_twiddles<M>(tw, a.tw, threadIdx.x, NT);
+  stage_twiddles<M, V>(tw, a.tw, threadIdx.x, NT);
   if constexpr (STAGE_AFTER_STORE) stage();
 
   for (int w = wb; w < we; ++w) {
@@ -419,7 +419,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
       reg[t] = (y >= in_lo && y < in_hi) ? lds_in[y] : make_float2(0.f, 0.f);
     }
     group_sync<M>();
-    fft<M, false, HALF>(reg, lds, j0, tw);
+    fft<M, false, HALF, V>(reg, lds, j0, tw);
 
     // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0:
     // read from the plan's table of H(|kx|, |ky|) when there is one, else evaluated here.
@@ -492,7 +492,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
         cur = nxt;
       }
     }
-    fft<M, true, false>(reg, lds, j0, tw);
+    fft<M, true, false, V>(reg, lds, j0, tw);
     group_sync<M>();
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
@@ -515,15 +515,15 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
   }
 }
 
-template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL>
+template <int M, int PAD, bool CONJ, int TX, int HM, bool FULL, int V = 0>
 __global__ void __launch_bounds__(TX * Geo<M>::P) __attribute__((amdgpu_waves_per_eu(4)))
 col_kernel(ColArgs a) {
   __shared__ float2 tile[TX * Geo<M>::COL_REGION];
-  __shared__ float2 tw[twiddle_count<M>()];
+  __shared__ float2 tw[twiddle_count<M, V>()];
   int bx, by;
   col_block_item(static_cast<int>(blockIdx.x + gridDim.x * blockIdx.y), static_cast<int>(gridDim.x * gridDim.y),
                  static_cast<int>(gridDim.x), bx, by);
-  col_body<M, PAD, CONJ, TX, HM, FULL>(a, bx, by, tile, tw);
+  col_body<M, PAD, CONJ, TX, HM, FULL, V>(a, bx, by, tile, tw);
 }
 
 // One launch of a column pass for several designs of the same transform length (see

@@ -36,7 +36,7 @@ class COpts(ctypes.Structure):
                 ("force_variant", ctypes.c_int32), ("transfer_table", ctypes.c_int32),
                 ("max_workspace_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("small_path", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("force_plan", ctypes.c_int32)]
 
 
 class CLayout(ctypes.Structure):
@@ -89,6 +89,12 @@ def load_library(path: str = LIB_PATH):
     lib.dpx_plan_variant.restype = ctypes.c_int
     lib.dpx_plan_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     lib.dpx_plan_schedule.restype = ctypes.c_int
+    lib.dpx_radix_plan_count.argtypes = [i32]
+    lib.dpx_radix_plan_count.restype = i32
+    lib.dpx_radix_plan_name.argtypes = [i32, i32]
+    lib.dpx_radix_plan_name.restype = ctypes.c_char_p
+    lib.dpx_plan_radix.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.dpx_plan_radix.restype = ctypes.c_int
     lib.dpx_loss_static.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     lib.dpx_loss_static.restype = ctypes.c_int
     lib.dpx_psnr.argtypes = [vp, vp, vp, vp, vp]
@@ -145,7 +151,7 @@ def _c_designs(designs):
 
 def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_bytes=0,
           autotune=0, streams=0, use_graph=0, schedule=0, transfer_table=0, small_path=0,
-          check_finite=0):
+          check_finite=0, force_plan=-1):
     o = COpts()
     lib.dpx_opts_default(ctypes.byref(o))
     o.checkpoint_mode = checkpoint_mode
@@ -159,6 +165,7 @@ def _opts(lib, checkpoint_mode=0, wl_chunk=0, force_variant=-1, max_workspace_by
     o.transfer_table = int(transfer_table)
     o.small_path = int(small_path)
     o.check_finite = int(check_finite)
+    o.force_plan = int(force_plan)
     return o
 
 
@@ -170,6 +177,12 @@ def plan_query(designs, **opts) -> int:
     out = ctypes.c_int64(0)
     _check(lib, lib.dpx_plan_query(arr, len(designs), ctypes.byref(o), ctypes.byref(out)))
     return int(out.value)
+
+
+def radix_plan_names(M: int) -> list:
+    """Names of the radix plans of transform length M (e.g. ["16x16x4", "8x8x16", ...])."""
+    lib = load_library()
+    return [lib.dpx_radix_plan_name(M, k).decode() for k in range(lib.dpx_radix_plan_count(M))]
 
 
 def variant_names():
@@ -195,7 +208,8 @@ class Plan:
     def __init__(self, designs: Sequence[dict], checkpoint_mode: int = 0, wl_chunk: int = 0,
                  force_variant: int = -1, max_workspace_bytes: int = 0, autotune: bool = False,
                  streams: int = 0, use_graph: bool = False, schedule: int = 0,
-                 transfer_table: int = 0, small_path: int = 0, check_finite: bool = False):
+                 transfer_table: int = 0, small_path: int = 0, check_finite: bool = False,
+                 force_plan: int = -1):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("dpx needs a HIP GPU (torch.cuda.is_available() is False)")
@@ -203,7 +217,7 @@ class Plan:
         self.designs = list(designs)
         arr, _keep = _c_designs(self.designs)
         o = _opts(self.lib, checkpoint_mode, wl_chunk, force_variant, max_workspace_bytes, autotune,
-                  streams, use_graph, schedule, transfer_table, small_path, check_finite)
+                  streams, use_graph, schedule, transfer_table, small_path, check_finite, force_plan)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.dpx_plan_create(arr, len(self.designs), ctypes.byref(o),
                                                   ctypes.byref(h)))
@@ -229,6 +243,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def radix(self, i: int = 0) -> tuple:
+        """(row-pass radix plan, column-pass radix plan) of design i."""
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib, self.lib.dpx_plan_radix(self._h, i, ctypes.byref(r), ctypes.byref(c)))
+        return r.value, c.value
 
     def variant(self, i: int = 0) -> int:
         v = ctypes.c_int32()
