@@ -17,12 +17,13 @@ namespace dpx {
 
 constexpr double kHalfPi = 1.57079632679489661923132169163975144;
 
-// returns (cos(2 pi rev), sin(2 pi rev)) / DEN; 1/DEN is folded into the coefficients, so a
-// power-of-two DEN costs nothing and changes no rounding.
+// returns (cos(pi r / 2), sin(pi r / 2)) / DEN for an angle of r quarter turns; 1/DEN is
+// folded into the coefficients, so a power-of-two DEN costs nothing and changes no rounding.
+// Callers whose argument is a product c x can pass (4 c) x: scaling by 4 is exact, so the bits
+// are those of cis_turns(c x) without the multiplication per element.
 template <int DEN = 1>
-__device__ __forceinline__ float2 cis_turns(double rev) {
+__device__ __forceinline__ float2 cis_quarter_turns(double r) {
   constexpr double sc = 1.0 / static_cast<double>(DEN);
-  const double r = 4.0 * rev;
   const double kq = rint(r);
   const float x = static_cast<float>(r - kq);
   const int q = static_cast<int>(kq);
@@ -47,6 +48,12 @@ __device__ __forceinline__ float2 cis_turns(double rev) {
   const unsigned flip_s = static_cast<unsigned>(q & 2) << 30;        // q = 2, 3
   return make_float2(__uint_as_float(__float_as_uint(cs) ^ flip_c),
                      __uint_as_float(__float_as_uint(sn) ^ flip_s));
+}
+
+// returns (cos(2 pi rev), sin(2 pi rev)) / DEN
+template <int DEN = 1>
+__device__ __forceinline__ float2 cis_turns(double rev) {
+  return cis_quarter_turns<DEN>(4.0 * rev);
 }
 
 // sqrt of a positive double to about 1e-14 relative: hardware reciprocal square root

@@ -11,6 +11,7 @@
         <kernel substring> <pass name> <command...>
     python -m paper_2604_02624_amd.profiling counters <A.csv> <B.csv> <fetch.csv> <write.csv> \\
         <copy_mib> <kernel substring> <command...>
+    python -m paper_2604_02624_amd.profiling valu <V1.csv> <V2.csv> <kernel substring> <command...>
 """
 from __future__ import annotations
 
@@ -142,11 +143,49 @@ def counters_markdown(a_csv: str, b_csv: str, fetch_csv: str, write_csv: str, co
     return "\n".join([f"Command (four passes): `{command}`", "", note, "", *rows, ""])
 
 
+VALU_TYPES = ["SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_TRANS_F32",
+              "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64",
+              "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64", "SQ_INSTS_VALU_CVT"]
+
+
+def valu_types_markdown(v1_csv: str, v2_csv: str, kernel_filter: str, command: str, top: int = 6) -> str:
+    """Vector instructions per wave by type, from two counter passes (the FP32 / FP64 adds,
+    multiplies, fused multiply-adds and transcendentals; then INT32, INT64, conversions, all
+    VALU, SQ_WAVES, LDS, SALU, VMEM reads), summed over the dispatches of each kernel."""
+    V1, V2 = _dispatch_counters(v1_csv), _dispatch_counters(v2_csv)
+    agg = defaultdict(lambda: defaultdict(float))
+    for D in (V1, V2):
+        for d in D.values():
+            if kernel_filter not in d["_kernel"]:
+                continue
+            for c, v in d.items():
+                if not c.startswith("_"):
+                    agg[d["_kernel"]][c] += v
+    rows = ["| kernel | VALU / wave | F32 add | F32 mul | F32 fma | F64 add | F64 mul | F64 fma | F64 trans | "
+            "INT32 | INT64 | cvt | other VALU | LDS / wave |",
+            "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    order = sorted(agg, key=lambda k: -agg[k].get("SQ_INSTS_VALU", 0.0))[:top]
+    for k in order:
+        a = agg[k]
+        w = max(a.get("SQ_WAVES", 0.0), 1.0)
+        per = {c: a.get(c, 0.0) / w for c in VALU_TYPES + ["SQ_INSTS_VALU", "SQ_INSTS_LDS"]}
+        other = per["SQ_INSTS_VALU"] - sum(per[c] for c in VALU_TYPES)
+        cells = [per[c] for c in ("SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_FMA_F32",
+                                  "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                                  "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64",
+                                  "SQ_INSTS_VALU_CVT")]
+        rows.append(f"| `{k[:64]}` | {per['SQ_INSTS_VALU']:.0f} | " + " | ".join(f"{c:.0f}" for c in cells) +
+                    f" | {other:.0f} | {per['SQ_INSTS_LDS']:.0f} |")
+    return "\n".join([f"Command (two passes): `{command}`", "", *rows, ""])
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats_markdown(argv[1], " ".join(argv[2:])))
     elif argv[0] == "counters":
         print(counters_markdown(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6], " ".join(argv[7:])))
+    elif argv[0] == "valu":
+        print(valu_types_markdown(argv[1], argv[2], argv[3], " ".join(argv[4:])))
     elif argv[0] == "traffic":
         rec = traffic_record(argv[1], argv[2], int(argv[3]), argv[4], argv[5], " ".join(argv[6:]))
         print(json.dumps(rec, indent=1))
