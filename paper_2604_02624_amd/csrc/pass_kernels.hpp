@@ -428,9 +428,18 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
     const double zq = 4.0 * a.zrev;
     auto H = [&](int ky) { return transfer<M, CONJ>(zq, base, ky); };
     if constexpr (HM == kHEval) {
+      // the product is selected, not H: outside the disc the element becomes +0 and the compiler
+      // branches the evaluation over runs of rows that lie wholly outside (a wavefront's rows are
+      // consecutive ky), which at long wavelengths on a fine pitch are most of the plane
       const int jv = opaque_lane_row(j0);
 #pragma unroll
-      for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], H(jv + P * t));
+      for (int t = 0; t < E; ++t) {
+        const int ky = jv + P * t;
+        const int kys = ky < M / 2 ? ky : ky - M;
+        const double q = base - static_cast<double>(kys * kys);
+        const float2 hh = cis_quarter_turns<M * M>(zq * sqrt_pos(q > 0.0 ? q : 1.0));
+        reg[t] = q > 0.0 ? cmul(reg[t], CONJ ? conjf2(hh) : hh) : make_float2(0.f, 0.f);
+      }
     } else if constexpr (HM == kHBand) {
       // band-limited angular spectrum: H = 0 where |kx| or |ky| exceeds the band limit
       // sqrt(q0 / (4 zrev^2 + 1)) (in frequency indices), beyond which the sampled phase aliases
