@@ -169,6 +169,38 @@ def test_zero_padded_every_transform_length(torch_dev, n):
     assert rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref) <= 1e-4
 
 
+@pytest.mark.parametrize("n", [64, 256])
+def test_mostly_evanescent_spectrum(torch_dev, n):
+    """A fine pitch against long wavelengths: the propagating disc covers a few percent of the
+    padded plane, so whole wavefronts of consecutive rows lie outside it (the evaluated transfer
+    function skips them).  Every column variant against the FP64 oracle and against each other."""
+    say(f"mostly evanescent spectrum, pad 2, N = {n}")
+    from paper_2604_02624_amd import dpx
+    g = np.random.default_rng(700 + n)
+    wl = np.array([700e-9, 800e-9, 900e-9])
+    d = wk.make_design(n=n, layers=2, wl=wl, n_mat=wk.cauchy_index(wl), dx=120e-9,
+                       z=[6e-6, 6e-6], fov=n // 2, pad=2)
+    # disc radius in frequency indices, M dx / lambda, against the half-width M / 2
+    assert (2 * n * 120e-9 / wl).max() < 0.35 * n
+    h = (g.random((2, n, n)) * 1.5e-6).astype(np.float32)
+    tau = g.random((3, n // 2, n // 2)).astype(np.float32)
+    I_ref = o.forward(d, h, None, "fft")
+    _, g_ref, _ = o.loss(I_ref, tau)
+    dh_ref = o.grad(d, h, None, g_ref, "fft")
+    outs = []
+    for v in range(4):
+        r = run_gpu(torch_dev, [d], [h], [tau], force_variant=v)
+        errs = per_wl_rel(r["I"].cpu().numpy().reshape(I_ref.shape), I_ref)
+        eg = rel_l2(r["dh"].cpu().numpy().reshape(h.shape), dh_ref)
+        say(f"{dpx.variant_names()[v]}: intensity rel L2 {errs.max():.2e}, dL/dh vs oracle adjoint {eg:.2e}")
+        assert errs.max() <= INT_TOL
+        assert eg <= 1e-4
+        outs.append(r)
+    for r in outs[1:]:
+        assert torch_dev.equal(r["I"], outs[0]["I"])
+        assert torch_dev.equal(r["dh"], outs[0]["dh"])
+
+
 def test_degenerate_zero_field_and_zero_target(torch_dev):
     say("zero input field (zero intensity) and an all-zero target: finite loss, zero gradient")
     g = np.random.default_rng(12)
