@@ -287,13 +287,14 @@ __device__ __forceinline__ int opaque_lane_row(int j0) {
   return j0;
 }
 
-// H(kx, ky) / M^2 with the conjugate for the adjoint; 0 outside the propagating disc.  zq is
-// 4 zrev, the phase in quarter turns per unit of sqrt(q) (the same bits as turns times 4).
+// H(kx, ky) / M^2 with the conjugate for the adjoint; 0 outside the propagating disc.  zrev is
+// the phase in revolutions per unit of sqrt(q); outside the disc q is replaced by the smallest
+// normal double (one maximum instead of two selects) and the result by 0.
 template <int M, bool CONJ>
-__device__ __forceinline__ float2 transfer(double zq, double base, int ky) {
+__device__ __forceinline__ float2 transfer(double zrev, double base, int ky) {
   const int kys = ky < M / 2 ? ky : ky - M;
   const double q = base - static_cast<double>(kys * kys);
-  const float2 hh = cis_quarter_turns<M * M>(zq * sqrt_pos(q > 0.0 ? q : 1.0));
+  const float2 hh = cis_turns_hw<M * M>(zrev * sqrt_pos(fmax(q, kMinNormalF64)));
   return q > 0.0 ? (CONJ ? conjf2(hh) : hh) : make_float2(0.f, 0.f);
 }
 
@@ -425,8 +426,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
     // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0:
     // read from the plan's table of H(|kx|, |ky|) when there is one, else evaluated here.
     const double base = c.q0 - static_cast<double>(kxs * kxs);
-    const double zq = 4.0 * a.zrev;
-    auto H = [&](int ky) { return transfer<M, CONJ>(zq, base, ky); };
+    auto H = [&](int ky) { return transfer<M, CONJ>(a.zrev, base, ky); };
     if constexpr (HM == kHEval) {
       // the product is selected, not H: outside the disc the element becomes +0 and the compiler
       // branches the evaluation over runs of rows that lie wholly outside (a wavefront's rows are
@@ -437,7 +437,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
         const int ky = jv + P * t;
         const int kys = ky < M / 2 ? ky : ky - M;
         const double q = base - static_cast<double>(kys * kys);
-        const float2 hh = cis_quarter_turns<M * M>(zq * sqrt_pos(q > 0.0 ? q : 1.0));
+        const float2 hh = cis_turns_hw<M * M>(a.zrev * sqrt_pos(fmax(q, kMinNormalF64)));
         reg[t] = q > 0.0 ? cmul(reg[t], CONJ ? conjf2(hh) : hh) : make_float2(0.f, 0.f);
       }
     } else if constexpr (HM == kHBand) {
@@ -470,17 +470,15 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
       // phase per element, z sqrt(q) - kx sx - ky sy in revolutions, reduced in FP64 like H's
       // own; conjugated for the adjoint.  Per element, so no lane holds ramp state and the
       // next wavelength's rows still fit in registers.
-      // in quarter turns: every term scaled by 4 (exact), the same bits as in turns times 4
-      const double sx4 = 4.0 * a.sx, sy4 = 4.0 * a.sy;
-      const double px = static_cast<double>(kxs) * sx4;
+      const double px = static_cast<double>(kxs) * a.sx;
       const int jv = opaque_lane_row(j0);
 #pragma unroll
       for (int t = 0; t < E; ++t) {
         const int ky = jv + P * t;
         const int kys = ky < M / 2 ? ky : ky - M;
         const double q = base - static_cast<double>(kys * kys);
-        const double ph = zq * sqrt_pos(q > 0.0 ? q : 1.0) - fma(static_cast<double>(kys), sy4, px);
-        const float2 hh = cis_quarter_turns<M * M>(ph);
+        const double ph = a.zrev * sqrt_pos(fmax(q, kMinNormalF64)) - fma(static_cast<double>(kys), a.sy, px);
+        const float2 hh = cis_turns_hw<M * M>(ph);
         reg[t] = q > 0.0 ? cmul(reg[t], CONJ ? conjf2(hh) : hh) : make_float2(0.f, 0.f);
       }
     } else if constexpr (HM == kHMirror) {
@@ -566,7 +564,7 @@ __global__ void __launch_bounds__(256) transfer_table_kernel(const WlConst* __re
   const int w = blockIdx.y;
   const double base = wl[w].q0 - static_cast<double>(kx * kx);
   float2* row = out + (static_cast<size_t>(w) * HS + kx) * HS;
-  for (int ky = threadIdx.x; ky < HS; ky += blockDim.x) row[ky] = transfer<M, false>(4.0 * zrev, base, ky);
+  for (int ky = threadIdx.x; ky < HS; ky += blockDim.x) row[ky] = transfer<M, false>(zrev, base, ky);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -647,12 +645,12 @@ __global__ void __launch_bounds__(gemm_threads(M)) colgemm_kernel(ColArgs a, con
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int ky = t0 * 16 + 4 * lk + r;
-        float2 z = cmul(make_float2(re0[r], im0[r]), transfer<M, CONJ>(4.0 * a.zrev, base, ky));
+        float2 z = cmul(make_float2(re0[r], im0[r]), transfer<M, CONJ>(a.zrev, base, ky));
         zr[ky * TN + lr] = z.x;
         zi[ky * TN + lr] = z.y;
         if (two) {
           ky = t1 * 16 + 4 * lk + r;
-          z = cmul(make_float2(re1[r], im1[r]), transfer<M, CONJ>(4.0 * a.zrev, base, ky));
+          z = cmul(make_float2(re1[r], im1[r]), transfer<M, CONJ>(a.zrev, base, ky));
           zr[ky * TN + lr] = z.x;
           zi[ky * TN + lr] = z.y;
         }
@@ -779,7 +777,7 @@ __device__ __forceinline__ void lds_columns(const WlConst& c, double zrev, int i
     const int kxs = kx < M / 2 ? kx : kx - M;
     const double base = c.q0 - static_cast<double>(kxs * kxs);
 #pragma unroll
-    for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], transfer<M, CONJ>(4.0 * zrev, base, j0 + P * t));
+    for (int t = 0; t < E; ++t) reg[t] = cmul(reg[t], transfer<M, CONJ>(zrev, base, j0 + P * t));
     fft<M, true, false>(reg, xr, j0, tw);
 #pragma unroll
     for (int t = 0; t < EN; ++t) plane[(j0 + P * t) * G::RS + kx] = reg[t];

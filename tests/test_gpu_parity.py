@@ -457,8 +457,15 @@ def test_recompute_mode_and_column_variants_agree(torch_dev):
         assert torch_dev.equal(r["I"], base["I"]), dpx.variant_names()[v]
         assert torch_dev.equal(r["dh"], base["dh"]), dpx.variant_names()[v]
     at = run_gpu(torch_dev, [d], [h], [tau], autotune=True)
-    say(f"autotuned variant {dpx.variant_names()[at['plan'].variant(0)]}")
-    assert torch_dev.equal(at["I"], base["I"])
+    radix = tuple(at["plan"].radix(0))
+    say(f"autotuned variant {dpx.variant_names()[at['plan'].variant(0)]}, radix plans {radix}")
+    if radix == (0, 0):
+        # the column variants give the same bits; so does the autotuned choice among them
+        assert torch_dev.equal(at["I"], base["I"])
+    else:
+        # another radix plan rounds differently: the same transform within the oracle tolerances
+        assert rel_l2(at["I"].cpu().numpy(), base["I"].cpu().numpy()) <= INT_TOL
+        assert rel_l2(at["dh"].cpu().numpy(), base["dh"].cpu().numpy()) <= 1e-4
 
 
 def test_variants_agree_on_every_transform_length(torch_dev):
