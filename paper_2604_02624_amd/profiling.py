@@ -161,9 +161,9 @@ def valu_types_markdown(v1_csv: str, v2_csv: str, kernel_filter: str, command: s
             for c, v in d.items():
                 if not c.startswith("_"):
                     agg[d["_kernel"]][c] += v
-    rows = ["| kernel | VALU / wave | F32 add | F32 mul | F32 fma | F64 add | F64 mul | F64 fma | F64 trans | "
-            "INT32 | INT64 | cvt | other VALU | LDS / wave |",
-            "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    rows = ["| kernel | VALU / wave | F32 add | F32 mul | F32 fma | F32 trans | F64 add | F64 mul | F64 fma | "
+            "F64 trans | INT32 | INT64 | cvt | other VALU | LDS / wave |",
+            "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     order = sorted(agg, key=lambda k: -agg[k].get("SQ_INSTS_VALU", 0.0))[:top]
     for k in order:
         a = agg[k]
@@ -171,7 +171,7 @@ def valu_types_markdown(v1_csv: str, v2_csv: str, kernel_filter: str, command: s
         per = {c: a.get(c, 0.0) / w for c in VALU_TYPES + ["SQ_INSTS_VALU", "SQ_INSTS_LDS"]}
         other = per["SQ_INSTS_VALU"] - sum(per[c] for c in VALU_TYPES)
         cells = [per[c] for c in ("SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_FMA_F32",
-                                  "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                                  "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
                                   "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64",
                                   "SQ_INSTS_VALU_CVT")]
         rows.append(f"| `{k[:64]}` | {per['SQ_INSTS_VALU']:.0f} | " + " | ".join(f"{c:.0f}" for c in cells) +
