@@ -148,16 +148,18 @@ def cpu_baseline(d, h, tau, budget_s, u_in=None, pool=None, threads=1):
                        f"thread, {threads} threads, {dt:.1f} s")
 
 
-def traffic_from_profiles(pass_name):
+def traffic_from_profiles(pass_name, workload, all_wavelengths, column_variant, column_plan):
     """HBM bytes per launch from the committed rocprofv3 counter runs of this pass, if they were
-    taken on the current kernel sources; else None."""
+    taken on this workload (all its wavelengths), with the same column variant and radix plan, on
+    the current kernel sources; else None."""
     from paper_2604_02624_amd.profiling import kernel_source_sha
     path = os.path.join(ROOT, "profiles", f"traffic_{pass_name}.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if (t.get("kernel_source_sha") != kernel_source_sha() or t.get("workload") != workload or not all_wavelengths
+            or t.get("column_variant") != column_variant or t.get("column_radix_plan") != column_plan):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -312,7 +314,7 @@ def main():
     flops_per_launch = pd["flops"] / nl
     tfs = flops_per_launch / per_launch_s / 1e12
     gbs = bytes_per_launch / per_launch_s / 1e9
-    traffic = traffic_from_profiles(dom)
+    traffic = traffic_from_profiles(dom, args.workload, args.wavelengths == 0, variant, radix["column"])
     roofline = dict(bound="hbm", kernel=dom, achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic,
                     algorithmic_bytes_per_launch=int(bytes_per_launch),

@@ -8,7 +8,7 @@
 
     python -m paper_2604_02624_amd.profiling stats <kernel_stats.csv> <command...>
     python -m paper_2604_02624_amd.profiling traffic <fetch.csv> <write.csv> <copy_mib> \\
-        <kernel substring> <pass name> <command...>
+        <kernel substring> <pass name> <workload> <column variant> <column radix plan> <command...>
     python -m paper_2604_02624_amd.profiling counters <A.csv> <B.csv> <fetch.csv> <write.csv> \\
         <copy_mib> <kernel substring> <command...>
     python -m paper_2604_02624_amd.profiling valu <V1.csv> <V2.csv> <kernel substring> <command...>
@@ -61,7 +61,9 @@ def _per_dispatch(csv_path: str, counter: str):
 
 
 def traffic_record(fetch_csv: str, write_csv: str, copy_mib: int, kernel_sub: str, pass_name: str,
-                   command: str) -> dict:
+                   command: str, workload: int = 4, column_variant: str = "", column_plan: str = "") -> dict:
+    """The record names the benchmark workload and column configuration it was taken on; bench.py
+    reports it only for that workload and configuration (and only on the same kernel sources)."""
     copy_bytes = copy_mib * (1 << 20)
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
     write = _per_dispatch(write_csv, "WRITE_SIZE")
@@ -76,7 +78,8 @@ def traffic_record(fetch_csv: str, write_csv: str, copy_mib: int, kernel_sub: st
     fk = [v * 1024 * f_scale for _, n, v in fetch if kernel_sub in n]
     wk = [v * 1024 * w_scale for _, n, v in write if kernel_sub in n]
     return dict(
-        kernel=kernel_sub, pass_name=pass_name, kernel_source_sha=kernel_source_sha(),
+        kernel=kernel_sub, pass_name=pass_name, workload=workload, column_variant=column_variant,
+        column_radix_plan=column_plan, kernel_source_sha=kernel_source_sha(),
         command=command, copy_bytes=copy_bytes,
         fetch_scale=round(f_scale, 4), write_scale=round(w_scale, 4),
         launches=len(fk),
@@ -187,7 +190,8 @@ def main(argv):
     elif argv[0] == "valu":
         print(valu_types_markdown(argv[1], argv[2], argv[3], " ".join(argv[4:])))
     elif argv[0] == "traffic":
-        rec = traffic_record(argv[1], argv[2], int(argv[3]), argv[4], argv[5], " ".join(argv[6:]))
+        rec = traffic_record(argv[1], argv[2], int(argv[3]), argv[4], argv[5], " ".join(argv[9:]),
+                             workload=int(argv[6]), column_variant=argv[7], column_plan=argv[8])
         print(json.dumps(rec, indent=1))
     else:
         raise SystemExit(__doc__)
