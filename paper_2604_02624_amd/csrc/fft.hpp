@@ -470,9 +470,10 @@ constexpr bool divides_or_multiple(int a, int b) { return a % b == 0 || b % a ==
 // of the padding period 2^SH, the padded address of output r splits exactly into a per-lane
 // base plus a compile-time offset, and the reads j0 + P t split the same way when P is a
 // multiple of 2^SH; the other stages compute the padded address directly.
-template <int M, int V, int ST, int R, int NS, bool LAST, bool INV, bool HALF>
+template <int M, int V, int ST, int R, int NS, bool LAST, bool INV, bool HALF, int CST = -1>
 __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds,
-                                               int j0, const float2* __restrict__ tw) {
+                                               int j0, const float2* __restrict__ tw,
+                                               const float2* treg = nullptr) {
   constexpr int E = Geo<M>::E;
   constexpr int P = Geo<M>::P;
   constexpr int S = E / R;
@@ -495,7 +496,8 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
       constexpr int OFF = twiddle_offset<M, V>(ST);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const float2 w = tw[OFF + (r - 1) * NS + k];
+        // stage CST: the lane's R - 1 twiddles are held in registers (treg), the same for all s
+        const float2 w = (ST == CST) ? treg[r - 1] : tw[OFF + (r - 1) * NS + k];
         v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
       }
     }
@@ -538,14 +540,40 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
   }
 }
 
-template <int M, int V, int ST, int NS, bool INV, bool HALF>
+template <int M, int V, int ST, int NS, bool INV, bool HALF, int CST = -1>
 __device__ __forceinline__ void fft_stages(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
-                                           const float2* __restrict__ tw) {
+                                           const float2* __restrict__ tw, const float2* treg = nullptr) {
   if constexpr (ST < Radix<M, V>::NST) {
     constexpr int R = Radix<M, V>::R[ST];
     constexpr bool LAST = (ST + 1 == Radix<M, V>::NST);
-    stockham_stage<M, V, ST, R, NS, LAST, INV, HALF && ST == 0>(reg, lds, j0, tw);
-    fft_stages<M, V, ST + 1, NS * R, INV, false>(reg, lds, j0, tw);
+    stockham_stage<M, V, ST, R, NS, LAST, INV, HALF && ST == 0, CST>(reg, lds, j0, tw, treg);
+    fft_stages<M, V, ST + 1, NS * R, INV, false, CST>(reg, lds, j0, tw, treg);
+  }
+}
+
+// The stage whose twiddles a caller may hold in registers: stage 1, when its twiddle index
+// k = j mod NS is the same for every butterfly of a lane (NS divides P) and it needs at most
+// seven values (radix 8); -1 when no stage qualifies.
+template <int M, int V>
+constexpr int register_twiddle_stage() {
+  return (Radix<M, V>::NST >= 3 && Radix<M, V>::R[1] <= 8 && Geo<M>::P % Radix<M, V>::R[0] == 0 &&
+          Geo<M>::WAVE_LOCAL) ? 1 : -1;
+}
+template <int M, int V>
+struct RegTwiddles {
+  static constexpr int STAGE = register_twiddle_stage<M, V>();
+  static constexpr int N = STAGE < 0 ? 1 : Radix<M, V>::R[1] - 1;  // registers (1 when unused)
+};
+
+// Loads the lane's twiddles of that stage from the table (in LDS) into treg.
+template <int M, int V>
+__device__ __forceinline__ void load_register_twiddles(float2* treg, const float2* __restrict__ tw,
+                                                       int j0) {
+  if constexpr (RegTwiddles<M, V>::STAGE >= 0) {
+    constexpr int NS = Radix<M, V>::R[0];
+    constexpr int OFF = twiddle_offset<M, V>(1);
+#pragma unroll
+    for (int r = 1; r < Radix<M, V>::R[1]; ++r) treg[r - 1] = tw[OFF + (r - 1) * NS + j0 % NS];
   }
 }
 
@@ -561,6 +589,20 @@ __device__ __forceinline__ void fft(float2 (&reg)[Geo<M>::E], float2* __restrict
     for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);
   }
   fft_stages<M, V, 0, 1, INV, H>(reg, lds, j0, tw);
+}
+
+// The same transform with the twiddles of register_twiddle_stage() taken from treg (loaded by
+// load_register_twiddles) instead of the table: the same values, so the same bits.
+template <int M, bool INV, bool HALF, int V = 0>
+__device__ __forceinline__ void fft_treg(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
+                                         const float2* __restrict__ tw,
+                                         const float2* treg) {
+  constexpr bool H = HALF && (Radix<M, V>::R[0] % 2 == 0);
+  if constexpr (HALF && !H) {
+#pragma unroll
+    for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);
+  }
+  fft_stages<M, V, 0, 1, INV, H, RegTwiddles<M, V>::STAGE>(reg, lds, j0, tw, treg);
 }
 
 }  // namespace dpx

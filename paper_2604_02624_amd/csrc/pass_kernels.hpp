@@ -403,12 +403,16 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
   stage_twiddles<M, V>(tw, a.tw, threadIdx.x, NT);
   if constexpr (STAGE_AFTER_STORE) stage();
 
+  // the twiddles of one stage stay in registers for the block's wavelengths (fewer LDS reads;
+  // loaded after the first barrier, which also orders the table's staging)
+  float2 treg[RegTwiddles<M, V>::N];
   for (int w = wb; w < we; ++w) {
     if constexpr (!STAGE_AFTER_STORE) {
       if constexpr (PREFETCH) stage();
       else fetch(w);
     }
     __syncthreads();
+    if (w == wb) load_register_twiddles<M, V>(treg, tw, j0);
     if constexpr (PREFETCH) {
       if (w + 1 < we) fetch(w + 1);
     }
@@ -421,7 +425,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
       reg[t] = (y >= in_lo && y < in_hi) ? lds_in[y] : make_float2(0.f, 0.f);
     }
     group_sync<M>();
-    fft<M, false, HALF, V>(reg, lds, j0, tw);
+    fft_treg<M, false, HALF, V>(reg, lds, j0, tw, treg);
 
     // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0:
     // read from the plan's table of H(|kx|, |ky|) when there is one, else evaluated here.
@@ -503,7 +507,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
         cur = nxt;
       }
     }
-    fft<M, true, false, V>(reg, lds, j0, tw);
+    fft_treg<M, true, false, V>(reg, lds, j0, tw, treg);
     group_sync<M>();
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
