@@ -552,12 +552,14 @@ __device__ __forceinline__ void fft_stages(float2 (&reg)[Geo<M>::E], float2* __r
 }
 
 // The stage whose twiddles a caller may hold in registers: stage 1, when its twiddle index
-// k = j mod NS is the same for every butterfly of a lane (NS divides P) and it needs at most
-// seven values (radix 8); -1 when no stage qualifies.
+// k = j mod NS is the same for every butterfly of a lane (NS divides P), it needs at most
+// seven values (radix 8) and one transform fills a wavefront (P = 64; with two per wavefront,
+// as at 512, the column kernels have no room for the registers and spill); -1 when no stage
+// qualifies.
 template <int M, int V>
 constexpr int register_twiddle_stage() {
-  return (Radix<M, V>::NST >= 3 && Radix<M, V>::R[1] <= 8 && Geo<M>::P % Radix<M, V>::R[0] == 0 &&
-          Geo<M>::WAVE_LOCAL) ? 1 : -1;
+  return (Radix<M, V>::NST >= 3 && Radix<M, V>::R[1] <= 8 && Geo<M>::P == 64 &&
+          Geo<M>::P % Radix<M, V>::R[0] == 0) ? 1 : -1;
 }
 template <int M, int V>
 struct RegTwiddles {
@@ -603,6 +605,14 @@ __device__ __forceinline__ void fft_treg(float2 (&reg)[Geo<M>::E], float2* __res
     for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);
   }
   fft_stages<M, V, 0, 1, INV, H, RegTwiddles<M, V>::STAGE>(reg, lds, j0, tw, treg);
+}
+
+// fft_treg when TREG, else fft (treg unused).
+template <int M, bool INV, bool HALF, int V, bool TREG>
+__device__ __forceinline__ void fft_sel(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
+                                        const float2* __restrict__ tw, const float2* treg) {
+  if constexpr (TREG) fft_treg<M, INV, HALF, V>(reg, lds, j0, tw, treg);
+  else fft<M, INV, HALF, V>(reg, lds, j0, tw);
 }
 
 }  // namespace dpx

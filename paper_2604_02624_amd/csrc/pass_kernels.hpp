@@ -404,7 +404,9 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
   if constexpr (STAGE_AFTER_STORE) stage();
 
   // the twiddles of one stage stay in registers for the block's wavelengths (fewer LDS reads;
-  // loaded after the first barrier, which also orders the table's staging)
+  // loaded after the first barrier, which also orders the table's staging) where the transfer
+  // function leaves room for them: the evaluated, table and translated sources would spill
+  constexpr bool TREG = (HM == kHMirror || HM == kHBand);
   float2 treg[RegTwiddles<M, V>::N];
   for (int w = wb; w < we; ++w) {
     if constexpr (!STAGE_AFTER_STORE) {
@@ -412,7 +414,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
       else fetch(w);
     }
     __syncthreads();
-    if (w == wb) load_register_twiddles<M, V>(treg, tw, j0);
+    if (TREG && w == wb) load_register_twiddles<M, V>(treg, tw, j0);
     if constexpr (PREFETCH) {
       if (w + 1 < we) fetch(w + 1);
     }
@@ -425,7 +427,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
       reg[t] = (y >= in_lo && y < in_hi) ? lds_in[y] : make_float2(0.f, 0.f);
     }
     group_sync<M>();
-    fft_treg<M, false, HALF, V>(reg, lds, j0, tw, treg);
+    fft_sel<M, false, HALF, V, TREG>(reg, lds, j0, tw, treg);
 
     // transfer function H = exp(+i 2 pi z sqrt(q)) / M^2 on the propagating disc, else 0:
     // read from the plan's table of H(|kx|, |ky|) when there is one, else evaluated here.
@@ -507,7 +509,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int bx, int by, float
         cur = nxt;
       }
     }
-    fft_treg<M, true, false, V>(reg, lds, j0, tw, treg);
+    fft_sel<M, true, false, V, TREG>(reg, lds, j0, tw, treg);
     group_sync<M>();
 #pragma unroll
     for (int t = 0; t < EN; ++t) {
