@@ -369,26 +369,43 @@ constexpr int radix_plans(int M) { return (M == 512 || M == 1024) ? 3 : 1; }
 // is a multiple of both P and the span NS R of the stage's butterflies, so every lane's writes
 // and reads stay a lane base plus compile-time offsets.  Chosen with the same 64-bank model as
 // the shift paddings: for the 1600-point transform, whose 80-lane groups span wavefronts, the
-// shift padding left about half of the exchange cycles in bank conflicts.
+// shift padding left about half of the exchange cycles in bank conflicts; at 1024 = 8 8 16 the
+// 32 lanes of one LDS cycle write only the NS = 8 twiddle columns k of stage 1 per output, which
+// the shift padding put on 8 bank pairs (4-way conflicts): 8 slots after every 64 spread the
+// four 64-entry groups of a half-wavefront over all 32 pairs.  The region (1148 slots, 28 mod
+// 32 so that the staged rows of the eight tile columns fall on distinct banks) keeps two
+// column blocks of 8 columns, 81.6 KB each with the twiddle table, within a CU's 160 KB.
 template <int M>
 struct XPad {
   static constexpr int A[4] = {0, 0, 0, 0};
   static constexpr int B[4] = {0, 0, 0, 0};
   static constexpr int REGION = 0;
   static constexpr int SKEW = 0;
+  static constexpr bool ROWS = true;  // the row passes use it too
+};
+template <> struct XPad<1024> {
+  static constexpr int A[4] = {0, 64, 0, 0};
+  static constexpr int B[4] = {0, 8, 0, 0};
+  static constexpr int REGION = 1148;
+  static constexpr int SKEW = 0;
+  // the row passes keep the shift padding: they run at the HBM rate, and the block padding's
+  // lane bases would take their forward middle pass over 128 registers
+  static constexpr bool ROWS = false;
 };
 template <> struct XPad<1600> {
   static constexpr int A[4] = {160, 400, 0, 0};
   static constexpr int B[4] = {1, 4, 0, 0};
   static constexpr int REGION = 1616;
   static constexpr int SKEW = 4;
+  static constexpr bool ROWS = true;
 };
 
 template <int M>
 struct Geo {
   static constexpr int E = Plan<M>::E;
   static constexpr int P = M / E;  // lanes per transform
-  static constexpr int ROW_REGION = XPad<M>::REGION > 0 ? XPad<M>::REGION : M + (M >> Plan<M>::SH) + Plan<M>::RX;
+  static constexpr int ROW_REGION = (XPad<M>::REGION > 0 && XPad<M>::ROWS) ? XPad<M>::REGION
+                                                                            : M + (M >> Plan<M>::SH) + Plan<M>::RX;
   static constexpr int COL_REGION = XPad<M>::REGION > 0 ? XPad<M>::REGION : M + (M >> Plan<M>::SH) + Plan<M>::CX;
   // the lanes of one transform lie in one wavefront
   static constexpr bool WAVE_LOCAL = P <= 64 && 64 % P == 0;
@@ -470,7 +487,7 @@ constexpr bool divides_or_multiple(int a, int b) { return a % b == 0 || b % a ==
 // of the padding period 2^SH, the padded address of output r splits exactly into a per-lane
 // base plus a compile-time offset, and the reads j0 + P t split the same way when P is a
 // multiple of 2^SH; the other stages compute the padded address directly.
-template <int M, int V, int ST, int R, int NS, bool LAST, bool INV, bool HALF, int CST = -1>
+template <int M, int V, int ST, int R, int NS, bool LAST, bool INV, bool HALF, int CST = -1, bool BP = true>
 __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds,
                                                int j0, const float2* __restrict__ tw,
                                                const float2* treg = nullptr) {
@@ -481,8 +498,8 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
   constexpr int S2 = 1 << SH;
   constexpr bool LIN_W = divides_or_multiple(NS, S2) && divides_or_multiple(NS * R, S2);
   constexpr bool LIN_R = (P % S2 == 0);
-  constexpr int XA = V == 0 ? XPad<M>::A[ST] : 0;
-  constexpr int XB = V == 0 ? XPad<M>::B[ST] : 0;
+  constexpr int XA = (V == 0 && BP) ? XPad<M>::A[ST] : 0;  // BP: the plan's block padding
+  constexpr int XB = (V == 0 && BP) ? XPad<M>::B[ST] : 0;
   static_assert(E % R == 0, "radix must divide the registers per lane");
   static_assert(XA == 0 || LAST || (XA % P == 0 && XA % (NS * R) == 0), "block padding must keep lanes linear");
 #pragma unroll
@@ -540,14 +557,14 @@ __device__ __forceinline__ void stockham_stage(float2 (&reg)[Geo<M>::E], float2*
   }
 }
 
-template <int M, int V, int ST, int NS, bool INV, bool HALF, int CST = -1>
+template <int M, int V, int ST, int NS, bool INV, bool HALF, int CST = -1, bool BP = true>
 __device__ __forceinline__ void fft_stages(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
                                            const float2* __restrict__ tw, const float2* treg = nullptr) {
   if constexpr (ST < Radix<M, V>::NST) {
     constexpr int R = Radix<M, V>::R[ST];
     constexpr bool LAST = (ST + 1 == Radix<M, V>::NST);
-    stockham_stage<M, V, ST, R, NS, LAST, INV, HALF && ST == 0, CST>(reg, lds, j0, tw, treg);
-    fft_stages<M, V, ST + 1, NS * R, INV, false, CST>(reg, lds, j0, tw, treg);
+    stockham_stage<M, V, ST, R, NS, LAST, INV, HALF && ST == 0, CST, BP>(reg, lds, j0, tw, treg);
+    fft_stages<M, V, ST + 1, NS * R, INV, false, CST, BP>(reg, lds, j0, tw, treg);
   }
 }
 
@@ -582,7 +599,7 @@ __device__ __forceinline__ void load_register_twiddles(float2* treg, const float
 // Full length-M transform of the group's registers with radix plan V.  HALF: elements
 // M/2..M-1 are zero (zero-padded input); only used when the first radix is even.  tw: the
 // plan's per-stage twiddle table (in LDS).
-template <int M, bool INV, bool HALF, int V = 0>
+template <int M, bool INV, bool HALF, int V = 0, bool BP = true>
 __device__ __forceinline__ void fft(float2 (&reg)[Geo<M>::E], float2* __restrict__ lds, int j0,
                                     const float2* __restrict__ tw) {
   constexpr bool H = HALF && (Radix<M, V>::R[0] % 2 == 0);
@@ -590,7 +607,7 @@ __device__ __forceinline__ void fft(float2 (&reg)[Geo<M>::E], float2* __restrict
 #pragma unroll
     for (int t = Geo<M>::E / 2; t < Geo<M>::E; ++t) reg[t] = make_float2(0.f, 0.f);
   }
-  fft_stages<M, V, 0, 1, INV, H>(reg, lds, j0, tw);
+  fft_stages<M, V, 0, 1, INV, H, -1, BP>(reg, lds, j0, tw);
 }
 
 // The same transform with the twiddles of register_twiddle_stage() taken from treg (loaded by

@@ -106,7 +106,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
       }
-      fft<M, false, HALF, V>(reg, lds, j0, tw);
+      fft<M, false, HALF, V, XPad<M>::ROWS>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
 #pragma unroll
@@ -121,7 +121,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false, V>(reg, lds, j0, tw);
+      fft<M, true, false, V, XPad<M>::ROWS>(reg, lds, j0, tw);
 #pragma unroll
       for (int t = 0; t < EN; ++t) reg[t] = cmul(reg[t], transmission(hreg[t], c));
       if (a.store_ckpt && active) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
 #pragma unroll
         for (int t = 0; t < EN; ++t) ck[j0 + P * t] = reg[t];
       }
-      fft<M, false, HALF, V>(reg, lds, j0, tw);
+      fft<M, false, HALF, V, XPad<M>::ROWS>(reg, lds, j0, tw);
       if (active) {
 #pragma unroll
         for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
@@ -145,7 +145,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false, V>(reg, lds, j0, tw);
+      fft<M, true, false, V, XPad<M>::ROWS>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.ofov + static_cast<size_t>(wc) * F * F + static_cast<size_t>(y - x0) * F;
 #pragma unroll
@@ -173,7 +173,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
           reg[t] = make_float2(0.f, 0.f);
         }
       }
-      fft<M, false, HALF, V>(reg, lds, j0, tw);
+      fft<M, false, HALF, V, XPad<M>::ROWS>(reg, lds, j0, tw);
       if (active) {
         float2* dst = a.spec + wc * plane + static_cast<size_t>(y) * M;
 #pragma unroll
@@ -200,7 +200,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
       float2 reg[E];
 #pragma unroll
       for (int t = 0; t < E; ++t) reg[t] = row[j0 + P * t];
-      fft<M, true, false, V>(reg, lds, j0, tw);
+      fft<M, true, false, V, XPad<M>::ROWS>(reg, lds, j0, tw);
       const float ct = static_cast<float>(c.ct);
       const float ca = static_cast<float>(c.ca);
 #pragma unroll
@@ -220,7 +220,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int by, float
         if constexpr (MODE == ROW_ADJ_MID) reg[t] = cmulc(gv, transmission(hreg[t], c));
       }
       if constexpr (MODE == ROW_ADJ_MID) {
-        fft<M, false, HALF, V>(reg, lds, j0, tw);
+        fft<M, false, HALF, V, XPad<M>::ROWS>(reg, lds, j0, tw);
         if (active) {
 #pragma unroll
           for (int t = 0; t < E; ++t) row[j0 + P * t] = reg[t];
