@@ -328,9 +328,12 @@ struct DFT {
 // ------------------------------------------------------------------------------------------
 // SH: the exchange index i is stored at i + (i >> SH) (one padding slot every 2^SH entries),
 // RX / CX: extra slots between the exchange regions of neighbouring transforms in the row /
-// column kernels.  Chosen with a bank model (64 four-byte banks, 8-byte accesses) so that
-// the scattered stage writes, the strided reads and the column kernel's tile transposes
-// touch each bank about as often as a conflict-free access would.
+// column kernels.  First chosen with a bank model of 64 four-byte banks serving 32 lanes per
+// cycle.  Measured on gfx950 (bank-conflict counters of a probe that writes and reads one
+// lane-address pattern at a time), 8-byte writes follow another model: 16 lanes per cycle
+// over 32 four-byte banks, so a quarter-wavefront's 32 dwords must fall on distinct banks
+// (stride-2 writes take twice the cycles, stride-16 ones 16 times), while 8-byte reads of the
+// same patterns show almost no conflicts.  The 1024-point plan is chosen with that model.
 template <int M>
 struct Plan;
 template <> struct Plan<64>   { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {16, 4, 0, 0}; };
@@ -340,7 +343,7 @@ template <> struct Plan<192>  { static constexpr int E = 12, NST = 3, SH = 3, RX
 template <> struct Plan<256>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 8;  static constexpr int R[4] = {16, 16, 0, 0}; };
 template <> struct Plan<384>  { static constexpr int E = 12, NST = 4, SH = 5, RX = 4, CX = 0;  static constexpr int R[4] = {12, 4, 4, 2}; };
 template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX = 16, CX = 16; static constexpr int R[4] = {8, 8, 8, 0}; };
-template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 5, RX = 0, CX = 4;  static constexpr int R[4] = {8, 8, 16, 0}; };
+template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 4, RX = 0, CX = 4;  static constexpr int R[4] = {8, 8, 16, 0}; };
 template <> struct Plan<1600> { static constexpr int E = 20, NST = 3, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {20, 20, 4, 0}; };
 
 // Radix plans: plan 0 of every length is Plan<M>::R; the lengths of the large workloads have
@@ -367,14 +370,15 @@ constexpr int radix_plans(int M) { return (M == 512 || M == 1024) ? 3 : 1; }
 // shift padding of Plan::SH; REGION then is the exchange region of every transform and SKEW the
 // offset of the staged column rows of tile column c, SKEW (c / 2) slots into its region.  A[s]
 // is a multiple of both P and the span NS R of the stage's butterflies, so every lane's writes
-// and reads stay a lane base plus compile-time offsets.  Chosen with the same 64-bank model as
-// the shift paddings: for the 1600-point transform, whose 80-lane groups span wavefronts, the
-// shift padding left about half of the exchange cycles in bank conflicts; at 1024 = 8 8 16 the
-// 32 lanes of one LDS cycle write only the NS = 8 twiddle columns k of stage 1 per output, which
-// the shift padding put on 8 bank pairs (4-way conflicts): 8 slots after every 64 spread the
-// four 64-entry groups of a half-wavefront over all 32 pairs.  The region (1148 slots, 28 mod
-// 32 so that the staged rows of the eight tile columns fall on distinct banks) keeps two
-// column blocks of 8 columns, 81.6 KB each with the twiddle table, within a CU's 160 KB.
+// and reads stay a lane base plus compile-time offsets.  For the 1600-point transform, whose
+// 80-lane groups span wavefronts, the shift padding left about half of the exchange cycles in
+// bank conflicts (chosen with the 64-bank model).  At 1024 = 8 8 16 (chosen with the measured
+// write model above), the 16 lanes of one write cycle hold only the NS = 8 twiddle columns k
+// of stage 1, so each output's writes of two 64-entry groups fell on the same banks (2-way):
+// 8 slots after every 64 move the second group by 16 banks.  Stage 0 takes the shift padding
+// with SH = 4, which is conflict-free for its writes.  The region, 1146 slots (2 mod 4, so
+// that the staged rows of the eight tile columns fall on distinct banks), keeps two column
+// blocks of 8 columns, 81.5 KB each with the twiddle table, within a CU's 160 KB.
 template <int M>
 struct XPad {
   static constexpr int A[4] = {0, 0, 0, 0};
@@ -386,7 +390,7 @@ struct XPad {
 template <> struct XPad<1024> {
   static constexpr int A[4] = {0, 64, 0, 0};
   static constexpr int B[4] = {0, 8, 0, 0};
-  static constexpr int REGION = 1148;
+  static constexpr int REGION = 1146;
   static constexpr int SKEW = 0;
   // the row passes keep the shift padding: they run at the HBM rate, and the block padding's
   // lane bases would take their forward middle pass over 128 registers
