@@ -370,10 +370,12 @@ constexpr int radix_plans(int M) { return (M == 512 || M == 1024) ? 3 : 1; }
 // shift padding of Plan::SH; REGION then is the exchange region of every transform and SKEW the
 // offset of the staged column rows of tile column c, SKEW (c / 2) slots into its region.  A[s]
 // is a multiple of both P and the span NS R of the stage's butterflies, so every lane's writes
-// and reads stay a lane base plus compile-time offsets.  For the 1600-point transform, whose
-// 80-lane groups span wavefronts, the shift padding left about half of the exchange cycles in
-// bank conflicts (chosen with the 64-bank model).  At 1024 = 8 8 16 (chosen with the measured
-// write model above), the 16 lanes of one write cycle hold only the NS = 8 twiddle columns k
+// and reads stay a lane base plus compile-time offsets.  Both plans are chosen with the
+// measured write model above.  For the 1600-point transform (20 20 4), whose 80-lane groups
+// span wavefronts, the 16 lanes of a write cycle store stage 0's outputs 20 entries apart
+// (4 distinct banks pairs without padding): one slot after every 80 entries separates them;
+// stage 1 takes 4 slots after every 400; 1622-slot regions put the staged rows of the eight
+// tile columns on distinct banks.  At 1024 = 8 8 16, the 16 lanes of one write cycle hold only the NS = 8 twiddle columns k
 // of stage 1, so each output's writes of two 64-entry groups fell on the same banks (2-way):
 // 8 slots after every 64 move the second group by 16 banks.  Stage 0 takes the shift padding
 // with SH = 4, which is conflict-free for its writes.  The region, 1146 slots (2 mod 4, so
@@ -397,10 +399,10 @@ template <> struct XPad<1024> {
   static constexpr bool ROWS = false;
 };
 template <> struct XPad<1600> {
-  static constexpr int A[4] = {160, 400, 0, 0};
+  static constexpr int A[4] = {80, 400, 0, 0};
   static constexpr int B[4] = {1, 4, 0, 0};
-  static constexpr int REGION = 1616;
-  static constexpr int SKEW = 4;
+  static constexpr int REGION = 1622;
+  static constexpr int SKEW = 0;
   static constexpr bool ROWS = true;
 };
 
