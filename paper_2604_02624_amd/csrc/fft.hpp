@@ -333,16 +333,19 @@ struct DFT {
 // lane-address pattern at a time), 8-byte writes follow another model: 16 lanes per cycle
 // over 32 four-byte banks, so a quarter-wavefront's 32 dwords must fall on distinct banks
 // (stride-2 writes take twice the cycles, stride-16 ones 16 times), while 8-byte reads of the
-// same patterns show almost no conflicts.  The 1024-point plan is chosen with that model.
+// same patterns show almost no conflicts.  The plans of 128 to 1024 points are chosen with
+// that model (the exchanges of the row and column kernels and the column kernels' staging);
+// 512 keeps SH = 4, with which its column kernels that evaluate H per element stay at 128
+// registers (SH = 3, conflict-free in its exchanges too, takes them to 144-150).
 template <int M>
 struct Plan;
 template <> struct Plan<64>   { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {16, 4, 0, 0}; };
 template <> struct Plan<96>   { static constexpr int E = 24, NST = 3, SH = 6, RX = 1, CX = 1;  static constexpr int R[4] = {3, 8, 4, 0}; };
-template <> struct Plan<128>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {16, 8, 0, 0}; };
-template <> struct Plan<192>  { static constexpr int E = 12, NST = 3, SH = 3, RX = 0, CX = 0;  static constexpr int R[4] = {12, 4, 4, 0}; };
-template <> struct Plan<256>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 8;  static constexpr int R[4] = {16, 16, 0, 0}; };
-template <> struct Plan<384>  { static constexpr int E = 12, NST = 4, SH = 5, RX = 4, CX = 0;  static constexpr int R[4] = {12, 4, 4, 2}; };
-template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX = 16, CX = 16; static constexpr int R[4] = {8, 8, 8, 0}; };
+template <> struct Plan<128>  { static constexpr int E = 16, NST = 2, SH = 3, RX = 1, CX = 1;  static constexpr int R[4] = {16, 8, 0, 0}; };
+template <> struct Plan<192>  { static constexpr int E = 12, NST = 3, SH = 2, RX = 0, CX = 2;  static constexpr int R[4] = {12, 4, 4, 0}; };
+template <> struct Plan<256>  { static constexpr int E = 16, NST = 2, SH = 4, RX = 0, CX = 2;  static constexpr int R[4] = {16, 16, 0, 0}; };
+template <> struct Plan<384>  { static constexpr int E = 12, NST = 4, SH = 2, RX = 0, CX = 2;  static constexpr int R[4] = {12, 4, 4, 2}; };
+template <> struct Plan<512>  { static constexpr int E = 16, NST = 3, SH = 4, RX = 16, CX = 2; static constexpr int R[4] = {8, 8, 8, 0}; };
 template <> struct Plan<1024> { static constexpr int E = 16, NST = 3, SH = 4, RX = 0, CX = 4;  static constexpr int R[4] = {8, 8, 16, 0}; };
 template <> struct Plan<1600> { static constexpr int E = 20, NST = 3, SH = 4, RX = 0, CX = 0;  static constexpr int R[4] = {20, 20, 4, 0}; };
 
