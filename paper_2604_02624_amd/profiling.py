@@ -12,6 +12,7 @@
     python -m paper_2604_02624_amd.profiling counters <A.csv> <B.csv> <fetch.csv> <write.csv> \\
         <copy_mib> <kernel substring> <command...>
     python -m paper_2604_02624_amd.profiling valu <V1.csv> <V2.csv> <kernel substring> <command...>
+    python -m paper_2604_02624_amd.profiling lds <counters.csv> <command...>
 """
 from __future__ import annotations
 
@@ -182,6 +183,64 @@ def valu_types_markdown(v1_csv: str, v2_csv: str, kernel_filter: str, command: s
     return "\n".join([f"Command (two passes): `{command}`", "", *rows, ""])
 
 
+# index patterns of probes/lds_bank_probe.hip (float2 slot of lane i), in its order
+LDS_PATTERNS = [
+    ("linear", lambda i: i),
+    ("stride 2", lambda i: 2 * i),
+    ("stride 4", lambda i: 4 * i),
+    ("stride 16", lambda i: 16 * i),
+    ("16-lane runs 32 apart", lambda i: i % 16 + 32 * (i // 16)),
+    ("4-lane runs 64 apart", lambda i: i % 4 + 64 * (i // 4)),
+    ("1024 stage-0 write, shift 5", lambda i: 8 * i + ((8 * i) >> 5)),
+    ("1024 stage-0 write, shift 4", lambda i: 8 * i + ((8 * i) >> 4)),
+    ("1024 stage-1 write, shift 5", lambda i: (i // 8) * 64 + i % 8 + (((i // 8) * 64 + i % 8) >> 5)),
+    ("1024 stage-1 write, 8 per 64", lambda i: (i // 8) * 64 + i % 8 + (((i // 8) * 64 + i % 8) // 64) * 8),
+    ("column staging, 1148-slot regions", lambda i: (i % 8) * 1148 + i // 8),
+    ("column staging, 1146-slot regions", lambda i: (i % 8) * 1146 + i // 8),
+]
+
+
+def lds_write_model_cycles(slots) -> int:
+    """Cycles of one 8-byte write of a wavefront under the model the probe fits: four groups of
+    16 lanes, each group as many cycles as the most dwords that fall on one of 32 banks."""
+    total = 0
+    for q in range(4):
+        banks = defaultdict(set)
+        for a in slots[16 * q:16 * q + 16]:
+            for d in (2 * a, 2 * a + 1):
+                banks[d % 32].add(d)
+        total += max(len(v) for v in banks.values())
+    return total
+
+
+def lds_markdown(csv_path: str, command: str) -> str:
+    """Per pattern: LDS cycles and bank-conflict cycles per access of the probe's write and read
+    kernels (the read kernel's 144 initial linear writes are taken out), next to the write model."""
+    agg = defaultdict(lambda: defaultdict(float))
+    for d in _dispatch_counters(csv_path).values():
+        name = d["_kernel"]
+        kind = "wr" if "wr_k<" in name else "rd" if "rd_k<" in name else None
+        if kind is None:
+            continue
+        pat = int(name.split("<")[1].split(">")[0])
+        for c in ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS"):
+            agg[(pat, kind)][c] += d[c]
+    rows = ["| pattern | write cycles | write conflict cycles | model write cycles | read cycles | read conflict cycles |",
+            "|---|---:|---:|---:|---:|---:|"]
+    for p, (label, f) in enumerate(LDS_PATTERNS):
+        w, r = agg.get((p, "wr")), agg.get((p, "rd"))
+        if not w or not r:
+            continue
+        wi = w["SQ_INSTS_LDS"]
+        # read kernel: 144 linear writes (4 cycles, no conflicts) per 2048 reads
+        ri = r["SQ_INSTS_LDS"] * 2048 / 2192
+        ract = (r["SQ_LDS_IDX_ACTIVE"] - 4 * r["SQ_INSTS_LDS"] * 144 / 2192) / ri
+        rows.append(f"| {label} | {w['SQ_LDS_IDX_ACTIVE'] / wi:.2f} | {w['SQ_LDS_BANK_CONFLICT'] / wi:.2f} | "
+                    f"{lds_write_model_cycles([f(i) for i in range(64)])} | {ract:.2f} | "
+                    f"{r['SQ_LDS_BANK_CONFLICT'] / ri:.2f} |")
+    return "\n".join([f"Command: `{command}`", "", *rows, ""])
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats_markdown(argv[1], " ".join(argv[2:])))
@@ -189,6 +248,8 @@ def main(argv):
         print(counters_markdown(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6], " ".join(argv[7:])))
     elif argv[0] == "valu":
         print(valu_types_markdown(argv[1], argv[2], argv[3], " ".join(argv[4:])))
+    elif argv[0] == "lds":
+        print(lds_markdown(argv[1], " ".join(argv[2:])))
     elif argv[0] == "traffic":
         rec = traffic_record(argv[1], argv[2], int(argv[3]), argv[4], argv[5], " ".join(argv[9:]),
                              workload=int(argv[6]), column_variant=argv[7], column_plan=argv[8])
