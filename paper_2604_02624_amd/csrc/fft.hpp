@@ -329,12 +329,13 @@ struct DFT {
 // SH: the exchange index i is stored at i + (i >> SH) (one padding slot every 2^SH entries),
 // RX / CX: extra slots between the exchange regions of neighbouring transforms in the row /
 // column kernels.  First chosen with a bank model of 64 four-byte banks serving 32 lanes per
-// cycle.  Measured on gfx950 (bank-conflict counters of a probe that writes and reads one
-// lane-address pattern at a time), 8-byte writes follow another model: 16 lanes per cycle
-// over 32 four-byte banks, so a quarter-wavefront's 32 dwords must fall on distinct banks
-// (stride-2 writes take twice the cycles, stride-16 ones 16 times), while 8-byte reads of the
-// same patterns show almost no conflicts.  The plans of 128 to 1024 points are chosen with
-// that model (the exchanges of the row and column kernels and the column kernels' staging);
+// cycle.  Measured on gfx950 (bank-conflict counters of probes/lds_bank_probe.hip, which
+// writes and reads one lane-address pattern at a time), 8-byte writes follow another model:
+// 16 lanes per cycle over 32 four-byte banks, so a quarter-wavefront's 32 dwords must fall on
+// distinct banks (stride-2 writes take twice the cycles, stride-16 ones 16 times), while
+// 8-byte reads of the same patterns show almost no conflicts.  The plans of 128 to 1024
+// points are chosen with that model (the exchanges of the row and column kernels and the
+// column kernels' staging);
 // 512 keeps SH = 4, with which its column kernels that evaluate H per element stay at 128
 // registers (SH = 3, conflict-free in its exchanges too, takes them to 144-150).
 template <int M>
@@ -376,11 +377,11 @@ constexpr int radix_plans(int M) { return (M == 512 || M == 1024) ? 3 : 1; }
 // and reads stay a lane base plus compile-time offsets.  Both plans are chosen with the
 // measured write model above.  For the 1600-point transform (20 20 4), whose 80-lane groups
 // span wavefronts, the 16 lanes of a write cycle store stage 0's outputs 20 entries apart
-// (4 distinct banks pairs without padding): one slot after every 80 entries separates them;
+// (4 distinct bank pairs without padding): one slot after every 80 entries separates them;
 // stage 1 takes 4 slots after every 400; 1622-slot regions put the staged rows of the eight
-// tile columns on distinct banks.  At 1024 = 8 8 16, the 16 lanes of one write cycle hold only the NS = 8 twiddle columns k
-// of stage 1, so each output's writes of two 64-entry groups fell on the same banks (2-way):
-// 8 slots after every 64 move the second group by 16 banks.  Stage 0 takes the shift padding
+// tile columns on distinct banks.  At 1024 = 8 8 16, the 16 lanes of one write cycle hold
+// only the NS = 8 twiddle columns k of stage 1, so each output's writes of two 64-entry groups
+// fell on the same banks (2-way): 8 slots after every 64 move the second group by 16 banks.  Stage 0 takes the shift padding
 // with SH = 4, which is conflict-free for its writes.  The region, 1146 slots (2 mod 4, so
 // that the staged rows of the eight tile columns fall on distinct banks), keeps two column
 // blocks of 8 columns, 81.5 KB each with the twiddle table, within a CU's 160 KB.
