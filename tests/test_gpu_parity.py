@@ -469,9 +469,12 @@ def test_recompute_mode_and_column_variants_agree(torch_dev):
 
 
 def test_variants_agree_on_every_transform_length(torch_dev):
-    say("column-pass variants, pad 2, N in {48, 96, 192}")
+    """Bitwise agreement of the column-pass variants: the evaluated and mirrored transfer
+    functions, 8- and 16-column tiles; at 1024 points the mirrored kernels hold stage-1
+    twiddles in registers and the others read them from the table (same values, same bits)."""
+    say("column-pass variants, pad 2, N in {48, 96, 192, 256, 512}")
     from paper_2604_02624_amd import dpx
-    for n in (48, 96, 192):
+    for n in (48, 96, 192, 256, 512):
         g = np.random.default_rng(300 + n)
         wl = np.array([450e-9, 600e-9, 750e-9])
         d = wk.make_design(n=n, layers=2, wl=wl, n_mat=1.5, dx=300e-9, z=[20e-6, 30e-6],
