@@ -30,7 +30,7 @@ METRIC = "wavelength·layer propagations/s (fwd+adjoint) + % HBM roofline vs pla
 UNIT = "propagations/s"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFS = 157.3
-# the issue ceiling of single FP32 operations (this build emits no packed FP32): 256 CUs x 4
+# the issue ceiling of single FP32 operations (the library emits no packed FP32): 256 CUs x 4
 # SIMDs x 16 lanes x 2 flops (fused multiply-add) x 2.4 GHz
 FP32_NONPACKED_PEAK_TFS = 78.6
 # kernel instances the per-pass timers report one by one (a pass kind of the row passes is one
@@ -209,7 +209,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
-              "the path shards over wavelengths with one all-reduce of dL/dh, which this build does "
+              "the path shards over wavelengths with one all-reduce of dL/dh, which the library does "
               "not run across GPUs.", file=sys.stderr)
         sys.exit(2)
 

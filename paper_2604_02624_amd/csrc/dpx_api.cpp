@@ -1034,7 +1034,7 @@ dpx_status join_lanes(dpx_plan* p, const Design& d, hipStream_t s) {
 // band-limit flag, timed chunk) key.  Kept per plan creation, and across processes in the text
 // file named by the environment variable DPX_TUNE_CACHE when it is set (one line per key:
 // "dpx-tune M pad band wc row_plan col_plan col_variant"; lines for lengths, plans or variants
-// this build does not have are ignored).
+// the library does not have are ignored).
 struct TuneChoice {
   int row_plan, col_plan, col_variant;
 };

@@ -116,7 +116,7 @@ def test_autotuner_picks_plans_and_keeps_them_in_its_cache_file(torch_dev, tmp_p
     assert plan.radix(0) == radix and plan.variant(0) == cv
     plan.close()
     assert len(cache.read_text().splitlines()) == 1
-    # a line for this build's lengths with a plan it does not have is ignored
+    # a line for a built length with a plan the library does not have is ignored
     cache.write_text("dpx-tune 1024 2 0 6 7 7 0\n")
     plan = dpx.Plan([d], autotune=True)
     assert all(0 <= x < 3 for x in plan.radix(0))
